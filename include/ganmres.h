@@ -1,0 +1,183 @@
+/*
+ * ganmres.h - C ABI of the MI355X (gfx950) GA-NGMRES transport-registration
+ * library (libganmres.so).
+ *
+ * The library evaluates, on one GPU, the reduced objective and gradient of
+ * the transport-constrained optimal control problem of He & Mang, "A
+ * generalized alternating NGMRES method for PDE-constrained optimization
+ * problems governed by transport equations" (eq. e:varopt and, for
+ * mass-preserving transport, eq. e:varopt-optimal-transport), the spectral
+ * preconditioner of the fixed-point map (eq. e:rpgd), and one iteration of
+ * GA-NGMRES (Alg. 3) around that map.
+ *
+ * Conventions shared by every call:
+ *   - Return value: GANMRES_OK (0) or a negative GANMRES_E* code.  Nothing is
+ *     thrown across the ABI; ganmres_last_error() describes the last failure
+ *     of a handle (static lifetime until the next call on that handle).
+ *   - Arrays are DEVICE pointers owned by the caller, contiguous C order.
+ *     A scalar field ("image") has shape (n[0], .., n[dim-1]) - the last axis
+ *     contiguous; a vector field ("velocity") has shape (dim, n[0], ..,
+ *     n[dim-1]), component c acting along axis c.  The element type is float
+ *     (GANMRES_F32) or double (GANMRES_F64) as chosen in the config.
+ *   - Scalars returned to the host are written through HOST pointers; calls
+ *     that return host scalars synchronise the handle's stream.
+ *   - All device work is enqueued on the stream given to ganmres_create (a
+ *     hipStream_t; NULL means the default stream).  One handle per stream;
+ *     a handle is not thread-safe.
+ *   - The library owns only its workspace, allocated in ganmres_create (and,
+ *     for the solver history, at the first ganmres_step) and released by
+ *     ganmres_destroy.
+ *
+ * Discretisation (Sec. 2.2): periodic box [0,2pi)^dim, n_i cells of size
+ * h_i = 2 pi / n_i, Fourier pseudo-spectral derivatives, semi-Lagrangian time
+ * stepping with n_t steps of h_t = 1/n_t and an explicit RK2 backtrace, cubic
+ * Lagrange (tricubic / bicubic) interpolation at departure points, trapezoidal
+ * rule in time.  Grid sizes must be of the form 2^a 3^b with 4 <= n_i <= 1024.
+ */
+#ifndef GANMRES_H
+#define GANMRES_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GANMRES_OK = 0,
+    GANMRES_EINVAL = -1,       /* invalid argument or configuration          */
+    GANMRES_ENOMEM = -2,       /* device allocation failed                   */
+    GANMRES_EDEVICE = -3,      /* a HIP call failed                          */
+    GANMRES_ENONFINITE = -4,   /* NaN/Inf in an objective, gradient or norm  */
+    GANMRES_ELINESEARCH = -5,  /* Armijo condition not met in max_backtracks */
+    GANMRES_ELSQ = -6,         /* least-squares coefficients not finite      */
+    GANMRES_ESTATE = -7        /* call out of order (e.g. nothing to reuse)  */
+};
+
+enum { GANMRES_ADVECTION = 0, GANMRES_CONTINUITY = 1 };
+enum { GANMRES_F32 = 0, GANMRES_F64 = 1 };
+enum { GANMRES_VARIANT_GA = 0, GANMRES_VARIANT_ALT = 1 };
+enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1 };
+
+typedef struct ganmres_handle ganmres_handle;
+
+typedef struct {
+    int dim;               /* 2 or 3                                            */
+    int n[3];              /* grid cells per axis (first dim entries used)      */
+    int nt;                /* time steps, >= 1                                  */
+    int model;             /* GANMRES_ADVECTION (eq. e:varopt) or
+                              GANMRES_CONTINUITY (eq. e:varopt-optimal-transport) */
+    int incompressible;    /* 1: Leray-projected gradient (Sec. 3.5)            */
+    int reg_order;         /* p in 1..3: l_p(k) = |k|^(2p) (H1, H2, H3 models)  */
+    double alpha;          /* regularisation weight, > 0                        */
+    int dtype;             /* GANMRES_F32 or GANMRES_F64                        */
+    int checkpoint_every;  /* keep every c-th state of the forward history (>=1) */
+} ganmres_config;
+
+typedef struct {
+    int w;                 /* window depth, >= 0 (w_k = min(k, w))              */
+    int sigma;             /* NGMRES steps per cycle, >= 0 (0: plain FP / RPGD) */
+    int tau;               /* fixed-point steps per cycle, >= 0                 */
+    double eps_rel;        /* stop when ||g||_inf <= eps_rel ||g(v^0)||_inf     */
+    int n_iter;            /* stop after n_iter updates                         */
+    double c_armijo;       /* Armijo constant (paper: 1e-4)                     */
+    int max_backtracks;    /* halvings before GANMRES_ELINESEARCH (e.g. 30)     */
+    double rho_cap;        /* cap on the stored step, <= 0 means none           */
+    int variant;           /* GANMRES_VARIANT_GA: FP when mod(k,s+t) >= sigma;
+                              GANMRES_VARIANT_ALT: FP when mod(k,s+t) < tau     */
+} ganmres_solver_params;
+
+#define GANMRES_MAX_WINDOW 64
+
+typedef struct {
+    int k;                 /* iterations completed after this call              */
+    int step_kind;         /* GANMRES_STEP_NGMRES or GANMRES_STEP_FP            */
+    int stop;              /* 1 when the stopping rule of Alg. 3 holds          */
+    int n_trials;          /* objective evaluations in this line search         */
+    int n_grad;            /* gradient evaluations in this call                 */
+    int n_beta;            /* number of valid entries in beta                   */
+    double J;              /* J(v^{k+1})                                        */
+    double J_q;            /* J(q(v^k))                                         */
+    double ginf;           /* ||g(v^{k+1})||_inf                                */
+    double g0inf;          /* ||g(v^0)||_inf                                    */
+    double rho;            /* accepted step                                     */
+    double beta[GANMRES_MAX_WINDOW + 1];
+} ganmres_step_info;
+
+/* Create a problem for template m0 and reference m1 (device images of cfg's
+ * shape and dtype; both are copied).  stream: hipStream_t or NULL.
+ * Errors: GANMRES_EINVAL (dim not 2/3, n_i not 2^a 3^b in [4,1024], nt < 1,
+ * alpha <= 0, reg_order not 1..3, model/dtype unknown, incompressible with the
+ * continuity model, checkpoint_every < 1), GANMRES_ENOMEM, GANMRES_EDEVICE. */
+int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1,
+                   void* stream, ganmres_handle** out);
+
+/* Release the handle and its workspace (NULL is accepted). */
+int ganmres_destroy(ganmres_handle* h);
+
+/* Message for the last failure on h (or of the last failed create if h is NULL). */
+const char* ganmres_last_error(const ganmres_handle* h);
+
+/* Objective J(v) = 1/2 ||m(1) - m1||_h^2 + alpha/2 <v, L_p v>_h (eq. e:varopt;
+ * <a,b>_h = prod(h_i) sum a b).  v: device velocity.  J: host, required.
+ * mismatch: host, nullable: 1/2 ||m(1) - m1||_h^2.
+ * keep_history = 1 keeps the state history, departure points and spectra
+ * of v for a following ganmres_eval_gradient(..., reuse_forward = 1).
+ * Errors: GANMRES_ENONFINITE. */
+int ganmres_eval_objective(ganmres_handle* h, const void* v, int keep_history,
+                           double* J, double* mismatch);
+
+/* Reduced gradient g(v) = alpha L_p v + b (eq. e:reduced-gradient) with
+ * b = int lam grad m dt (advection, adjoint eq. e:adjoint with final value
+ * lam(1) = m1 - m(1)), b = -int pi grad lam dt (continuity), and b replaced
+ * by its Leray projection when incompressible.  g is the L2 representer: a
+ * grid function with dJ(v)[d] ~ <g, d>_h.  v, g: device velocities (may not
+ * alias).  reuse_forward = 1: the caller asserts that the last
+ * ganmres_eval_objective(keep_history = 1) was for this same v, and its forward
+ * solve is reused.  J: host, nullable.
+ * Errors: GANMRES_ESTATE (reuse without a kept history), GANMRES_ENONFINITE. */
+int ganmres_eval_gradient(ganmres_handle* h, const void* v, void* g,
+                          int reuse_forward, double* J);
+
+/* Search direction of the preconditioned fixed-point map (eqs. e:rpgd,
+ * e:fixedpoint): s = -(alpha L_p)^-1 g, the zero symbol entry replaced by
+ * one (Sec. 2.2), Leray-projected when incompressible.  g, s: device
+ * velocities (may alias).  gs: host, nullable: <g, s>_h. */
+int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs);
+
+/* One iteration k of GA-NGMRES(w; sigma, tau) (Alg. 3) around the line-searched
+ * map q(v) = v + rho s (eqs. e:linesearch, e:armijo).  v: device velocity, in:
+ * v^k, out: v^{k+1}.  On the first call after create or reset, v is v^0 and
+ * g(v^0) is evaluated first.  The handle keeps k, the stored step rho, the
+ * last w+1 pairs (v, g) and ||g(v^0)||_inf.  info: host, nullable.
+ * Errors: GANMRES_EINVAL (w < 0 or > GANMRES_MAX_WINDOW, sigma = tau = 0,
+ * negative counts), GANMRES_ELINESEARCH, GANMRES_ELSQ, GANMRES_ENONFINITE. */
+int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
+                 ganmres_step_info* info);
+
+/* Forget the solver state (k, rho, history); the next ganmres_step starts a
+ * new solve from the v it is given. */
+int ganmres_solver_reset(ganmres_handle* h);
+
+/* Copy a field of the last forward/adjoint solve into out (device image):
+ * which = 0: state m^j, which = 1: adjoint lam^j (j in 0..nt).  The state is
+ * available after any objective or gradient evaluation, the adjoint after a
+ * gradient evaluation.  Errors: GANMRES_EINVAL, GANMRES_ESTATE. */
+int ganmres_get_field(ganmres_handle* h, int which, int j, void* out);
+
+/* Kernel timing.  With on = 1 the library brackets every launch with HIP
+ * events on its stream and accumulates per-kernel-class device time.
+ * ganmres_timing_get returns the accumulated milliseconds and launch count of
+ * class `kernel` (see ganmres_kernel_name) and the number of classes;
+ * ganmres_timing_reset clears the accumulators. */
+int ganmres_timing_enable(ganmres_handle* h, int on);
+int ganmres_timing_reset(ganmres_handle* h);
+int ganmres_timing_get(ganmres_handle* h, int kernel, double* ms, long long* launches);
+int ganmres_kernel_count(void);
+const char* ganmres_kernel_name(int kernel);
+
+/* Device bytes held by the handle's workspace. */
+long long ganmres_workspace_bytes(const ganmres_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GANMRES_H */

@@ -1,0 +1,279 @@
+"""Thin Python binding of libganmres.so, the MI355X GA-NGMRES transport library.
+
+Argument marshalling only: every step of the objective, gradient,
+preconditioner and GA-NGMRES iteration runs in the library's HIP kernels.
+torch supplies device memory and the stream.  There is no fallback: if the
+library is missing or a call fails, an exception is raised.
+
+Shapes: an image is a tensor of shape (n_1, ..., n_d), a velocity one of shape
+(d, n_1, ..., n_d), contiguous, float32 or float64 on the GPU, matching the
+problem's dtype.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_lib", "libganmres.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "ganmres.h")
+
+ADVECTION, CONTINUITY = 0, 1
+F32, F64 = 0, 1
+VARIANT_GA, VARIANT_ALT = 0, 1
+STEP_NGMRES, STEP_FP = 0, 1
+MAX_WINDOW = 64
+
+ERRORS = {
+    -1: "GANMRES_EINVAL", -2: "GANMRES_ENOMEM", -3: "GANMRES_EDEVICE",
+    -4: "GANMRES_ENONFINITE", -5: "GANMRES_ELINESEARCH", -6: "GANMRES_ELSQ",
+    -7: "GANMRES_ESTATE",
+}
+
+
+class GanmresError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("n", ctypes.c_int * 3), ("nt", ctypes.c_int),
+                ("model", ctypes.c_int), ("incompressible", ctypes.c_int),
+                ("reg_order", ctypes.c_int), ("alpha", ctypes.c_double),
+                ("dtype", ctypes.c_int), ("checkpoint_every", ctypes.c_int)]
+
+
+class SolverParams(ctypes.Structure):
+    _fields_ = [("w", ctypes.c_int), ("sigma", ctypes.c_int), ("tau", ctypes.c_int),
+                ("eps_rel", ctypes.c_double), ("n_iter", ctypes.c_int),
+                ("c_armijo", ctypes.c_double), ("max_backtracks", ctypes.c_int),
+                ("rho_cap", ctypes.c_double), ("variant", ctypes.c_int)]
+
+
+class StepInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int), ("step_kind", ctypes.c_int), ("stop", ctypes.c_int),
+                ("n_trials", ctypes.c_int), ("n_grad", ctypes.c_int), ("n_beta", ctypes.c_int),
+                ("J", ctypes.c_double), ("J_q", ctypes.c_double), ("ginf", ctypes.c_double),
+                ("g0inf", ctypes.c_double), ("rho", ctypes.c_double),
+                ("beta", ctypes.c_double * (MAX_WINDOW + 1))]
+
+
+_lib = None
+
+
+def lib():
+    """Load libganmres.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2510_08782_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
+    L.ganmres_create.argtypes = [ctypes.POINTER(Config), vp, vp, vp, ctypes.POINTER(vp)]
+    L.ganmres_destroy.argtypes = [vp]
+    L.ganmres_last_error.argtypes = [vp]
+    L.ganmres_last_error.restype = ctypes.c_char_p
+    L.ganmres_eval_objective.argtypes = [vp, vp, ip, dp, dp]
+    L.ganmres_eval_gradient.argtypes = [vp, vp, vp, ip, dp]
+    L.ganmres_apply_precond.argtypes = [vp, vp, vp, dp]
+    L.ganmres_step.argtypes = [vp, ctypes.POINTER(SolverParams), vp, ctypes.POINTER(StepInfo)]
+    L.ganmres_solver_reset.argtypes = [vp]
+    L.ganmres_get_field.argtypes = [vp, ip, ip, vp]
+    L.ganmres_timing_enable.argtypes = [vp, ip]
+    L.ganmres_timing_reset.argtypes = [vp]
+    L.ganmres_timing_get.argtypes = [vp, ip, dp, ctypes.POINTER(ctypes.c_longlong)]
+    L.ganmres_kernel_count.argtypes = []
+    L.ganmres_kernel_name.argtypes = [ip]
+    L.ganmres_kernel_name.restype = ctypes.c_char_p
+    L.ganmres_workspace_bytes.argtypes = [vp]
+    L.ganmres_workspace_bytes.restype = ctypes.c_longlong
+    _lib = L
+    return L
+
+
+def header_symbols():
+    """Function names declared in include/ganmres.h."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    return sorted(set(re.findall(r"\b(ganmres_[a-z_]+)\s*\(", txt)))
+
+
+@dataclass
+class SolveParams:
+    w: int = 5
+    sigma: int = 2
+    tau: int = 1
+    eps_rel: float = 1e-2
+    n_iter: int = 200
+    c_armijo: float = 1e-4
+    max_backtracks: int = 30
+    rho_cap: float = 0.0
+    variant: int = VARIANT_GA
+
+    def to_c(self):
+        return SolverParams(self.w, self.sigma, self.tau, self.eps_rel, self.n_iter,
+                            self.c_armijo, self.max_backtracks, self.rho_cap, self.variant)
+
+
+class Problem:
+    """A registration problem living on one GPU (one library handle).
+
+    m0, m1: device images; the library copies them.  The handle's stream is
+    torch's current stream at construction."""
+
+    def __init__(self, m0, m1, nt, alpha, reg_order, model="advection",
+                 incompressible=False, checkpoint_every=1, stream=None):
+        import torch
+        if not m0.is_cuda:
+            raise ValueError("m0/m1 must be device tensors")
+        self.torch = torch
+        self.dtype = m0.dtype
+        if m0.dtype not in (torch.float32, torch.float64) or m1.dtype != m0.dtype:
+            raise ValueError("m0/m1 must share dtype float32 or float64")
+        self.m0 = m0.contiguous()
+        self.m1 = m1.contiguous()
+        self.shape = tuple(m0.shape)
+        self.dim = len(self.shape)
+        n = list(self.shape) + [1] * (3 - self.dim)
+        cfg = Config(self.dim, (ctypes.c_int * 3)(*n), int(nt),
+                     ADVECTION if model == "advection" else CONTINUITY,
+                     int(bool(incompressible)), int(reg_order), float(alpha),
+                     F32 if m0.dtype == torch.float32 else F64, int(checkpoint_every))
+        self.cfg = cfg
+        self.nt = int(nt)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(m0.device)
+        h = ctypes.c_void_p()
+        rc = lib().ganmres_create(ctypes.byref(cfg), self.m0.data_ptr(), self.m1.data_ptr(),
+                                  ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise GanmresError(rc, lib().ganmres_last_error(None).decode())
+        self.h = h
+
+    def _check(self, rc):
+        if rc != 0:
+            raise GanmresError(rc, lib().ganmres_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().ganmres_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _vec(self, v):
+        if v.dtype != self.dtype or tuple(v.shape) != (self.dim,) + self.shape or not v.is_cuda:
+            raise ValueError(f"expected a {self.dtype} device tensor of shape "
+                             f"{(self.dim,) + self.shape}")
+        if not v.is_contiguous():
+            raise ValueError("velocity must be contiguous")
+        return v
+
+    def new_velocity(self):
+        return self.torch.zeros((self.dim,) + self.shape, dtype=self.dtype, device=self.m0.device)
+
+    # -- calls ----------------------------------------------------------------
+    def eval_objective(self, v, keep_history=False, with_mismatch=False):
+        J, mis = ctypes.c_double(), ctypes.c_double()
+        self._check(lib().ganmres_eval_objective(self.h, self._vec(v).data_ptr(),
+                                                 int(keep_history), ctypes.byref(J),
+                                                 ctypes.byref(mis)))
+        return (J.value, mis.value) if with_mismatch else J.value
+
+    def eval_gradient(self, v, g=None, reuse_forward=False):
+        g = self.new_velocity() if g is None else self._vec(g)
+        J = ctypes.c_double()
+        self._check(lib().ganmres_eval_gradient(self.h, self._vec(v).data_ptr(), g.data_ptr(),
+                                                int(reuse_forward), ctypes.byref(J)))
+        return J.value, g
+
+    def apply_precond(self, g, s=None):
+        s = self.new_velocity() if s is None else self._vec(s)
+        gs = ctypes.c_double()
+        self._check(lib().ganmres_apply_precond(self.h, self._vec(g).data_ptr(), s.data_ptr(),
+                                                ctypes.byref(gs)))
+        return s, gs.value
+
+    def step(self, params: SolveParams, v):
+        info = StepInfo()
+        cp = params.to_c()
+        self._check(lib().ganmres_step(self.h, ctypes.byref(cp), self._vec(v).data_ptr(),
+                                       ctypes.byref(info)))
+        return info
+
+    def reset(self):
+        self._check(lib().ganmres_solver_reset(self.h))
+
+    def get_field(self, which, j):
+        out = self.torch.empty(self.shape, dtype=self.dtype, device=self.m0.device)
+        self._check(lib().ganmres_get_field(self.h, {"state": 0, "adjoint": 1}[which], int(j),
+                                            out.data_ptr()))
+        return out
+
+    def workspace_bytes(self):
+        return int(lib().ganmres_workspace_bytes(self.h))
+
+    # -- timing ---------------------------------------------------------------
+    def timing(self, on=True):
+        self._check(lib().ganmres_timing_enable(self.h, int(on)))
+
+    def timing_reset(self):
+        self._check(lib().ganmres_timing_reset(self.h))
+
+    def timing_report(self):
+        out = {}
+        for kidx in range(lib().ganmres_kernel_count()):
+            ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+            self._check(lib().ganmres_timing_get(self.h, kidx, ctypes.byref(ms), ctypes.byref(cnt)))
+            out[lib().ganmres_kernel_name(kidx).decode()] = (ms.value, cnt.value)
+        return out
+
+    def solve(self, params: SolveParams, v0=None, callback=None):
+        """Run GA-NGMRES from v0 (default 0) until the stopping rule holds."""
+        v = self.new_velocity() if v0 is None else self._vec(v0).clone()
+        self.reset()
+        infos = []
+        while True:
+            info = self.step(params, v)
+            infos.append(info)
+            if callback:
+                callback(info)
+            if info.stop:
+                break
+        return v, infos
+
+
+def transport_objective():
+    """torch.autograd.Function whose forward is the library's objective and
+    whose backward is the hand-written adjoint: dJ/dv = |h| g (g is the L2
+    representer returned by ganmres_eval_gradient)."""
+    import math
+
+    import torch
+
+    class TransportObjective(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, v, problem):
+            v = v.detach().contiguous()
+            J = problem.eval_objective(v, keep_history=True)
+            ctx.problem = problem
+            ctx.save_for_backward(v)
+            return torch.tensor(J, dtype=torch.float64, device=v.device)
+
+        @staticmethod
+        def backward(ctx, grad_out):
+            (v,) = ctx.saved_tensors
+            problem = ctx.problem
+            _, g = problem.eval_gradient(v, reuse_forward=True)
+            cell = 1.0
+            for n in problem.shape:
+                cell *= 2.0 * math.pi / n
+            return (grad_out.to(g.dtype) * cell) * g, None
+
+    return TransportObjective

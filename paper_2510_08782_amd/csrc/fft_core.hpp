@@ -1,0 +1,151 @@
+// Mixed-radix (8/4/2/3) Stockham autosort FFT on data resident in LDS.
+//
+// Layout: PC pencils of length L interleaved as buf[i * PC + p], so that the
+// threads of a wavefront that share a butterfly index j touch consecutive
+// words.  One pass of radix R turns the L/R length-R sub-transforms of the
+// current stage into sub-transforms of length Ns*R:
+//   inputs  a_r = in[j + r L/R]                      (r = 0..R-1)
+//   twiddle a_r *= W^(k r L/(Ns R)),  k = j mod Ns,  W = exp(dir 2 pi i / L)
+//   a R-point DFT with sign dir, then
+//   outputs out[(j / Ns) Ns R + k + r Ns]
+// which leaves the result in natural order after the last pass.
+// dir = -1: forward (unnormalised), dir = +1: inverse (unnormalised).
+#pragma once
+
+#include "common.hpp"
+
+namespace gan {
+
+template <typename T, int R>
+__host__ __device__ inline void dft_small(C2<T>* a, int dir) {
+    const T s = static_cast<T>(dir);
+    if constexpr (R == 2) {
+        C2<T> t0 = a[0];
+        a[0] = cadd(t0, a[1]);
+        a[1] = csub(t0, a[1]);
+    } else if constexpr (R == 3) {
+        const T c3 = static_cast<T>(0.86602540378443864676);  // sqrt(3)/2
+        C2<T> t1 = cadd(a[1], a[2]);
+        C2<T> t2 = csub(a[0], cscale(t1, static_cast<T>(0.5)));
+        C2<T> t3 = cmuli(csub(a[1], a[2]), s * c3);
+        a[0] = cadd(a[0], t1);
+        a[1] = cadd(t2, t3);
+        a[2] = csub(t2, t3);
+    } else if constexpr (R == 4) {
+        C2<T> s02 = cadd(a[0], a[2]);
+        C2<T> d02 = csub(a[0], a[2]);
+        C2<T> s13 = cadd(a[1], a[3]);
+        C2<T> d13 = cmuli(csub(a[1], a[3]), s);  // dir * i * (a1 - a3)
+        a[0] = cadd(s02, s13);
+        a[2] = csub(s02, s13);
+        a[1] = cadd(d02, d13);
+        a[3] = csub(d02, d13);
+    } else if constexpr (R == 8) {
+        // two radix-4 DFTs on even and odd samples, then a radix-2 merge
+        const T h = static_cast<T>(0.70710678118654752440);
+        C2<T> e[4] = {a[0], a[2], a[4], a[6]};
+        C2<T> o[4] = {a[1], a[3], a[5], a[7]};
+        dft_small<T, 4>(e, dir);
+        dft_small<T, 4>(o, dir);
+        // twiddles exp(dir 2 pi i q / 8), q = 0..3
+        C2<T> o1 = cmk(h * (o[1].x - s * o[1].y), h * (o[1].y + s * o[1].x));
+        C2<T> o2 = cmuli(o[2], s);
+        C2<T> o3 = cmk(h * (-o[3].x - s * o[3].y), h * (-o[3].y + s * o[3].x));
+        a[0] = cadd(e[0], o[0]);
+        a[4] = csub(e[0], o[0]);
+        a[1] = cadd(e[1], o1);
+        a[5] = csub(e[1], o1);
+        a[2] = cadd(e[2], o2);
+        a[6] = csub(e[2], o2);
+        a[3] = cadd(e[3], o3);
+        a[7] = csub(e[3], o3);
+    }
+}
+
+// One butterfly (index t in [0, PC * L / R)) of a Stockham pass.
+template <typename T, int R>
+__host__ __device__ inline void stockham_butterfly(const C2<T>* in, C2<T>* out, int t, int L,
+                                                   int pcshift, int Ns, const C2<T>* tw, int dir) {
+    const int PC = 1 << pcshift;
+    const int p = t & (PC - 1);
+    const int j = t >> pcshift;
+    const int nb = L / R;
+    const int k = j % Ns;
+    C2<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = in[((j + r * nb) << pcshift) + p];
+    if (Ns > 1) {
+        const int step = L / (Ns * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C2<T> w = tw[k * r * step];
+            if (dir > 0) w.y = -w.y;
+            a[r] = cmul(a[r], w);
+        }
+    }
+    dft_small<T, R>(a, dir);
+    const int base = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[((base + r * Ns) << pcshift) + p] = a[r];
+}
+
+template <typename T>
+__host__ __device__ inline void stockham_dispatch(int R, const C2<T>* in, C2<T>* out, int t, int L,
+                                                  int pcshift, int Ns, const C2<T>* tw, int dir) {
+    switch (R) {
+        case 8: stockham_butterfly<T, 8>(in, out, t, L, pcshift, Ns, tw, dir); break;
+        case 4: stockham_butterfly<T, 4>(in, out, t, L, pcshift, Ns, tw, dir); break;
+        case 3: stockham_butterfly<T, 3>(in, out, t, L, pcshift, Ns, tw, dir); break;
+        default: stockham_butterfly<T, 2>(in, out, t, L, pcshift, Ns, tw, dir); break;
+    }
+}
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// Whole transform of the PC pencils held in LDS buffer a (b is scratch of the
+// same size).  Returns the buffer holding the result.  Ends with a barrier.
+template <typename T>
+__device__ inline C2<T>* block_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, int pcshift, int dir) {
+    int Ns = 1;
+    for (int s = 0; s < pl.nrad; ++s) {
+        const int R = pl.rad[s];
+        const int nbt = (pl.L / R) << pcshift;
+        for (int t = threadIdx.x; t < nbt; t += blockDim.x)
+            stockham_dispatch<T>(R, a, b, t, pl.L, pcshift, Ns, pl.tw, dir);
+        __syncthreads();
+        C2<T>* tmp = a;
+        a = b;
+        b = tmp;
+        Ns *= R;
+    }
+    return a;
+}
+#endif
+
+// Radix plan: as many 8s as possible (keeping the rest a power of two
+// product), then 4, 2, and 3.  Returns the number of radices, 0 if L is not
+// of the form 2^a 3^b.
+inline int make_radices(int L, int* rad) {
+    int n = 0;
+    int m = L;
+    int p2 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++p2;
+    }
+    int p3 = 0;
+    while (m % 3 == 0) {
+        m /= 3;
+        ++p3;
+    }
+    if (m != 1) return 0;
+    while (p2 >= 3) {
+        rad[n++] = 8;
+        p2 -= 3;
+    }
+    if (p2 == 2) rad[n++] = 4;
+    if (p2 == 1) rad[n++] = 2;
+    for (int i = 0; i < p3; ++i) rad[n++] = 3;
+    return n;
+}
+
+}  // namespace gan

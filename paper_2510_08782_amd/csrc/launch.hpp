@@ -1,0 +1,93 @@
+// Host-side launchers of the library's kernels (one per kernel family).
+// Every launcher enqueues on `st` and returns the hipError_t of the launch.
+#pragma once
+
+#include "common.hpp"
+
+namespace gan {
+
+// ---- semi-Lagrangian kernels (sl.hip) --------------------------------------
+// RK2 departure displacements (index units) for velocity +v (dX) and -v (dY,
+// nullable).  s[c] = h_t / h_c converts component c to cells per step.
+template <typename T>
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, T* dX, T* dY,
+                                  hipStream_t st);
+// out = [fac *] I[src](i + disp)
+template <typename T>
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, T* out,
+                          hipStream_t st);
+// out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
+template <typename T>
+hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
+                                double sgn, T* out, hipStream_t st);
+
+// ---- reductions and vector kernels (vec.hip) -------------------------------
+// Deterministic two-stage FP64 reductions; the result lands in res[0] (device).
+int reduction_blocks(long long n);
+// sum (a - b)^2 ; if lam != nullptr also writes lam = b - a
+template <typename T>
+hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, long long n, double* partial,
+                             double* res, hipStream_t st);
+template <typename T>
+hipError_t launch_dot(const T* a, const T* b, long long n, double* partial, double* res,
+                      hipStream_t st);
+// max |a| with NaN mapped to +inf
+template <typename T>
+hipError_t launch_maxabs(const T* a, long long n, double* partial, double* res, hipStream_t st);
+// Gram matrix of K <= 8 vectors: res holds the K(K+1)/2 upper-triangle entries
+// (a, b >= a) in row order
+template <typename T>
+hipError_t launch_gram(const T* const* vecs, int K, long long n, double* partial, double* res,
+                       hipStream_t st);
+// out = a + s b
+template <typename T>
+hipError_t launch_axpy(const T* a, double s, const T* b, T* out, long long n, hipStream_t st);
+// out = q + sum_i c[i] (q - x[i])   (K <= 65; the NGMRES update)
+template <typename T>
+hipError_t launch_combine(const T* q, const T* const* x, const double* c, int K, T* out,
+                          long long n, hipStream_t st);
+
+// ---- spectral kernels (spectral.hip) ----------------------------------------
+template <typename T>
+struct SpectralPlans {
+    FftPlan<T> p[3];  // one plan per internal axis (length n[a])
+};
+
+// Body-force / divergence derivative along internal axis `axis`:
+//   out = [out +] sum_t w[t] * G_t * d/dx_axis F_t     (G_t = 1 when G == nullptr)
+// F_t = F + t*fstride, G_t = G + t*gstride, t = 0..ntime-1.
+template <typename T>
+hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axis, const T* F,
+                             long long fstride, const T* G, long long gstride, const double* w,
+                             int ntime, int accumulate, T* out, hipStream_t st);
+// Forward real-to-half-spectrum transform of `count` fields (count <= 3):
+// in[c] (real TI, N) -> out[c] (complex TC, NH), computed in precision TC.
+template <typename TI, typename TC>
+hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* const* in,
+                       C2<TC>* const* out, int count, hipStream_t st);
+// Inverse: spec[c] (overwritten) -> out[c] = scale * real(ifft) [+ add[c]]
+template <typename T>
+hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const* spec,
+                        T* const* out, const T* const* add, double scale, int count,
+                        hipStream_t st);
+
+struct SpecOpParams {
+    int dim;
+    int p;             // regulariser order
+    double alpha;
+    int leray;         // apply the Leray projection
+};
+// gh[c] = alpha l_p vh[c] + P bh[c]   (bh may alias gh; vh is an FP64 spectrum)
+template <typename T>
+hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
+                                C2<T>* const* bh, C2<T>* const* gh, hipStream_t st);
+// sh[c] = -P gh[c] / (alpha lbar_p)   (in place allowed)
+template <typename T>
+hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
+                               C2<T>* const* sh, hipStream_t st);
+// res[0] = sum_c sum_k l_p(k) |vh_c(k)|^2 over the full spectrum (half-spectrum weights)
+template <typename T>
+hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* const* vh,
+                                double* partial, double* res, hipStream_t st);
+
+}  // namespace gan

@@ -1,0 +1,53 @@
+// Deterministic FP64 block reductions (wavefront shuffles, fixed tree).
+#pragma once
+
+#include "common.hpp"
+
+namespace gan {
+
+__device__ inline double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_down(x, o, 64);
+    return x;
+}
+__device__ inline double wave_max(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = fmax(x, __shfl_down(x, o, 64));
+    return x;
+}
+
+// Block-wide sum (or max) of one value per thread; the result is valid in
+// thread 0.  sh must hold blockDim.x / 64 doubles.  Every thread must call it.
+template <bool MAX>
+__device__ inline double block_reduce(double x, double* sh) {
+    const int lane = threadIdx.x & 63;
+    const int wid = threadIdx.x >> 6;
+    x = MAX ? wave_max(x) : wave_sum(x);
+    if (lane == 0) sh[wid] = x;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x == 0) {
+        r = sh[0];
+        const int nw = (blockDim.x + 63) >> 6;
+        for (int i = 1; i < nw; ++i) r = MAX ? fmax(r, sh[i]) : r + sh[i];
+    }
+    __syncthreads();
+    return r;
+}
+
+// Stage 2: res[q] = fold of partial[q*nb .. q*nb + nb) for q < nq (one block
+// of 1024 threads).
+template <bool MAX>
+__global__ void __launch_bounds__(1024) finish_kernel(const double* __restrict__ partial, int nb,
+                                                      int nq, double* __restrict__ res) {
+    __shared__ double sh[1024 / 64];
+    for (int q = 0; q < nq; ++q) {
+        double x = 0.0;
+        for (int i = threadIdx.x; i < nb; i += blockDim.x)
+            x = MAX ? fmax(x, partial[(long long)q * nb + i]) : x + partial[(long long)q * nb + i];
+        const double r = block_reduce<MAX>(x, sh);
+        if (threadIdx.x == 0) res[q] = r;
+    }
+}
+
+}  // namespace gan

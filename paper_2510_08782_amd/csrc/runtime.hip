@@ -1,0 +1,886 @@
+// Runtime of the GA-NGMRES transport library: workspace, the reduced
+// objective / gradient pipeline, the preconditioned fixed-point map with
+// Armijo backtracking, and one GA-NGMRES iteration (the C ABI of ganmres.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <deque>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/ganmres.h"
+#include "fft_core.hpp"
+#include "launch.hpp"
+
+namespace gan {
+
+// Kernel classes for the optional event timing.
+enum KernelClass {
+    KC_CHAR = 0,   // RK2 characteristics
+    KC_SL,         // semi-Lagrangian gather step (state and adjoint)
+    KC_FACTOR,     // source factors
+    KC_DERIV,      // per-axis spectral derivative (body force, divergence)
+    KC_RFFT,       // full forward transform
+    KC_IRFFT,      // full inverse transform
+    KC_SPEC,       // pointwise spectral operators
+    KC_REDUCE,     // FP64 reductions (mismatch, dots, Gram, norms)
+    KC_VEC,        // axpy / NGMRES update
+    KC_COUNT
+};
+static const char* kKernelNames[KC_COUNT] = {"characteristics", "sl_step",    "source_factor",
+                                             "deriv_axis",      "rfft",       "irfft",
+                                             "spectral_op",     "reduction",  "vector_update"};
+
+struct Status {
+    int code = GANMRES_OK;
+    std::string msg;
+};
+
+class Error {
+   public:
+    Error(int c, std::string m) : code(c), msg(std::move(m)) {}
+    int code;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw ::gan::Error(e_ == hipErrorOutOfMemory ? GANMRES_ENOMEM : GANMRES_EDEVICE, \
+                               std::string(#expr) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    void alloc(size_t b) {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (b == 0) return;
+        HIPCHK(hipMalloc(&p, b));
+        bytes = b;
+    }
+};
+
+// ---- small dense FP64 least squares (host) ----------------------------------
+// Solve M beta = y (M symmetric positive semi-definite, n <= 65): Cholesky,
+// unless it fails or the squared pivot ratio is below 1e-12; then the eigen
+// pseudo-inverse with cutoff 1e-12 lambda_max (cyclic Jacobi).
+static constexpr double kLsqCutoff = 1e-12;
+
+static bool cholesky_solve(int n, const std::vector<double>& M, const std::vector<double>& y,
+                           std::vector<double>& x) {
+    std::vector<double> L(n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = M[j * n + j];
+        for (int k = 0; k < j; ++k) d -= L[j * n + k] * L[j * n + k];
+        if (!(d > 0.0)) return false;
+        const double ljj = std::sqrt(d);
+        L[j * n + j] = ljj;
+        for (int i = j + 1; i < n; ++i) {
+            double s = M[i * n + j];
+            for (int k = 0; k < j; ++k) s -= L[i * n + k] * L[j * n + k];
+            L[i * n + j] = s / ljj;
+        }
+    }
+    double pmin = INFINITY, pmax = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double p = L[j * n + j] * L[j * n + j];
+        pmin = std::min(pmin, p);
+        pmax = std::max(pmax, p);
+    }
+    if (pmin < kLsqCutoff * pmax) return false;
+    std::vector<double> z(n);
+    for (int i = 0; i < n; ++i) {
+        double s = y[i];
+        for (int k = 0; k < i; ++k) s -= L[i * n + k] * z[k];
+        z[i] = s / L[i * n + i];
+    }
+    x.assign(n, 0.0);
+    for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        for (int k = i + 1; k < n; ++k) s -= L[k * n + i] * x[k];
+        x[i] = s / L[i * n + i];
+    }
+    return true;
+}
+
+static void eigen_pinv_solve(int n, const std::vector<double>& M, const std::vector<double>& y,
+                             std::vector<double>& x) {
+    std::vector<double> A = M, V(n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += A[i * n + j] * A[i * n + j];
+                if (i != j) off += A[i * n + j] * A[i * n + j];
+            }
+        if (off <= 1e-30 * tot || off == 0.0) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[p * n + q];
+                if (apq == 0.0) continue;
+                const double theta = (A[q * n + q] - A[p * n + p]) / (2.0 * apq);
+                const double t = (theta >= 0 ? 1.0 : -1.0) /
+                                 (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {
+                    const double akp = A[k * n + p], akq = A[k * n + q];
+                    A[k * n + p] = c * akp - s * akq;
+                    A[k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double apk = A[p * n + k], aqk = A[q * n + k];
+                    A[p * n + k] = c * apk - s * aqk;
+                    A[q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[k * n + p], vkq = V[k * n + q];
+                    V[k * n + p] = c * vkp - s * vkq;
+                    V[k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    double lmax = 0.0;
+    for (int i = 0; i < n; ++i) lmax = std::max(lmax, A[i * n + i]);
+    x.assign(n, 0.0);
+    for (int e = 0; e < n; ++e) {
+        const double lam = A[e * n + e];
+        if (!(lam > kLsqCutoff * lmax)) continue;
+        double proj = 0.0;
+        for (int k = 0; k < n; ++k) proj += V[k * n + e] * y[k];
+        for (int k = 0; k < n; ++k) x[k] += V[k * n + e] * proj / lam;
+    }
+}
+
+// beta from the packed upper-triangle Gram of u = [r, g_0, ..., g_{n-1}].
+static std::vector<double> lsq_from_gram(int K, const std::vector<double>& G) {
+    const int n = K - 1;
+    const double Grr = G[0];
+    std::vector<double> M(n * n), y(n), x;
+    for (int i = 0; i < n; ++i) {
+        const double Gri = G[i + 1];
+        y[i] = -(Grr - Gri);
+        for (int j = 0; j < n; ++j) {
+            const double Grj = G[j + 1];
+            M[i * n + j] = Grr - Gri - Grj + G[(i + 1) * K + (j + 1)];
+        }
+    }
+    if (!cholesky_solve(n, M, y, x)) eigen_pinv_solve(n, M, y, x);
+    return x;
+}
+
+// ---- the problem -----------------------------------------------------------
+class ProblemBase {
+   public:
+    virtual ~ProblemBase() = default;
+    virtual double objective(const void* v, bool keep, double* mismatch) = 0;
+    virtual double gradient(const void* v, void* g, bool reuse) = 0;
+    virtual double precond(const void* g, void* s) = 0;
+    virtual void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) = 0;
+    virtual void reset() = 0;
+    virtual void get_field(int which, int j, void* out) = 0;
+    virtual long long workspace_bytes() const = 0;
+    // timing
+    bool timing = false;
+    double tms[KC_COUNT] = {};
+    long long tcount[KC_COUNT] = {};
+    virtual void timing_flush() = 0;
+};
+
+template <typename T>
+class Problem : public ProblemBase {
+   public:
+    using CT = C2<T>;
+    ganmres_config cfg;
+    Dims dm{};
+    hipStream_t st;
+    int d;
+    long long N, NH;
+    double h[3], cell, ht;
+    double cscale[3];  // h_t / h_c per component
+    SpectralPlans<T> plans{};
+    SpectralPlans<double> plans64{};  // the FP64 spectrum of v (regulariser)
+    std::vector<std::unique_ptr<DevBuf>> bufs;
+    DevBuf twbuf[3], twbuf64[3];
+    T *m0, *m1, *mhist, *lam, *dX, *dY, *delta, *cfac, *bfac, *b, *tmp;
+    C2<double>* vh[3];
+    CT* wh[3];
+    double *partial, *dres;
+    double* hres;  // pinned host results
+    long long ws_bytes = 0;
+    bool fwd_valid = false;
+    const void* fwd_v = nullptr;
+    bool adj_valid = false;
+    bool y_valid = false;
+    double reg_cached = 0.0;
+
+    // solver
+    int wcap = -1;
+    std::vector<std::unique_ptr<DevBuf>> ring_v, ring_g;
+    std::unique_ptr<DevBuf> qb, gqb, sb;
+    std::deque<int> hist;
+    bool started = false;
+    int k = 0;
+    double rho_bar = 1.0, g0inf = 0.0, Jcur = 0.0;
+
+    // timing events
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
+
+    T* alloc_T(long long n) {
+        bufs.emplace_back(new DevBuf);
+        bufs.back()->alloc(sizeof(T) * (size_t)n);
+        ws_bytes += sizeof(T) * n;
+        return static_cast<T*>(bufs.back()->p);
+    }
+    CT* alloc_C(long long n) {
+        bufs.emplace_back(new DevBuf);
+        bufs.back()->alloc(sizeof(CT) * (size_t)n);
+        ws_bytes += sizeof(CT) * n;
+        return static_cast<CT*>(bufs.back()->p);
+    }
+
+    Problem(const ganmres_config& c, const void* m0_in, const void* m1_in, hipStream_t s)
+        : cfg(c), st(s) {
+        d = c.dim;
+        dm.dim = d;
+        dm.n[0] = d == 3 ? c.n[0] : 1;
+        dm.n[1] = d == 3 ? c.n[1] : c.n[0];
+        dm.n[2] = d == 3 ? c.n[2] : c.n[1];
+        dm.N = (long long)dm.n[0] * dm.n[1] * dm.n[2];
+        dm.n2h = dm.n[2] / 2 + 1;
+        dm.NH = (long long)dm.n[0] * dm.n[1] * dm.n2h;
+        N = dm.N;
+        NH = dm.NH;
+        cell = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            h[a] = 2.0 * M_PI / dm.n[a];
+            if (a >= 3 - d) cell *= h[a];
+        }
+        ht = 1.0 / c.nt;
+        for (int cc = 0; cc < d; ++cc) cscale[cc] = ht / h[comp_axis(d, cc)];
+        // FFT plans and FP64 twiddles
+        for (int a = 3 - d; a < 3; ++a) {
+            FftPlan<T>& pl = plans.p[a];
+            pl.L = dm.n[a];
+            pl.nrad = make_radices(pl.L, pl.rad);
+            std::vector<CT> tw(pl.L);
+            for (int m = 0; m < pl.L; ++m) {
+                const double ang = -2.0 * M_PI * m / pl.L;
+                tw[m] = cmk(T(std::cos(ang)), T(std::sin(ang)));
+            }
+            twbuf[a].alloc(sizeof(CT) * pl.L);
+            HIPCHK(hipMemcpyAsync(twbuf[a].p, tw.data(), sizeof(CT) * pl.L, hipMemcpyHostToDevice, st));
+            pl.tw = static_cast<const CT*>(twbuf[a].p);
+            FftPlan<double>& p64 = plans64.p[a];
+            p64.L = pl.L;
+            p64.nrad = pl.nrad;
+            for (int r = 0; r < kMaxRadices; ++r) p64.rad[r] = pl.rad[r];
+            std::vector<C2<double>> tw64(pl.L);
+            for (int m = 0; m < pl.L; ++m) {
+                const double ang = -2.0 * M_PI * m / pl.L;
+                tw64[m] = cmk(std::cos(ang), std::sin(ang));
+            }
+            twbuf64[a].alloc(sizeof(C2<double>) * pl.L);
+            HIPCHK(hipMemcpyAsync(twbuf64[a].p, tw64.data(), sizeof(C2<double>) * pl.L,
+                                  hipMemcpyHostToDevice, st));
+            p64.tw = static_cast<const C2<double>*>(twbuf64[a].p);
+        }
+        const int nt = c.nt;
+        m0 = alloc_T(N);
+        m1 = alloc_T(N);
+        mhist = alloc_T((nt + 1) * N);
+        lam = alloc_T((nt + 1) * N);
+        dX = alloc_T(d * N);
+        dY = alloc_T(d * N);
+        const bool compressible = !c.incompressible;
+        delta = compressible ? alloc_T(N) : nullptr;
+        cfac = (compressible && c.model == GANMRES_CONTINUITY) ? alloc_T(N) : nullptr;
+        bfac = (compressible && c.model == GANMRES_ADVECTION) ? alloc_T(N) : nullptr;
+        b = alloc_T(d * N);
+        tmp = alloc_T(d * N);
+        for (int cc = 0; cc < 3; ++cc) {
+            vh[cc] = nullptr;
+            if (cc < d) {
+                bufs.emplace_back(new DevBuf);
+                bufs.back()->alloc(sizeof(C2<double>) * (size_t)NH);
+                ws_bytes += sizeof(C2<double>) * NH;
+                vh[cc] = static_cast<C2<double>*>(bufs.back()->p);
+            }
+            wh[cc] = cc < d ? alloc_C(NH) : nullptr;
+        }
+        {
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(double) * 64 * 1024);
+            partial = static_cast<double*>(bufs.back()->p);
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(double) * 128);
+            dres = static_cast<double*>(bufs.back()->p);
+        }
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 128, hipHostMallocDefault));
+        HIPCHK(hipMemcpyAsync(m0, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(m1, m1_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(mhist, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    ~Problem() override {
+        if (hres) (void)hipHostFree(hres);
+        for (auto& e : ev_pool) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    }
+
+    long long workspace_bytes() const override {
+        long long s = ws_bytes;
+        for (auto& r : ring_v) s += r->bytes;
+        for (auto& r : ring_g) s += r->bytes;
+        if (qb) s += qb->bytes + gqb->bytes + sb->bytes;
+        return s;
+    }
+
+    // -- timing -------------------------------------------------------------
+    void tbegin(int kind) {
+        if (!timing) return;
+        if (ev_used == ev_pool.size()) {
+            hipEvent_t a, b2;
+            HIPCHK(hipEventCreate(&a));
+            HIPCHK(hipEventCreate(&b2));
+            ev_pool.push_back({a, b2});
+            ev_kind.push_back(kind);
+        }
+        ev_kind[ev_used] = kind;
+        HIPCHK(hipEventRecord(ev_pool[ev_used].first, st));
+    }
+    void tend() {
+        if (!timing) return;
+        HIPCHK(hipEventRecord(ev_pool[ev_used].second, st));
+        ++ev_used;
+        if (ev_used >= 4096) timing_flush();
+    }
+    void timing_flush() override {
+        if (ev_used == 0) return;
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < ev_used; ++i) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second));
+            tms[ev_kind[i]] += ms;
+            tcount[ev_kind[i]] += 1;
+        }
+        ev_used = 0;
+    }
+
+    template <typename F>
+    void run(int kind, F&& f) {
+        tbegin(kind);
+        HIPCHK(f());
+        tend();
+    }
+
+    double fetch(int nvals = 1) {
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * nvals, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return hres[0];
+    }
+
+    const T* comp(const void* v, int c) const { return static_cast<const T*>(v) + c * N; }
+    T* comp(void* v, int c) const { return static_cast<T*>(v) + c * N; }
+
+    SpecOpParams specop(bool leray) const {
+        SpecOpParams s;
+        s.dim = d;
+        s.p = cfg.reg_order;
+        s.alpha = cfg.alpha;
+        s.leray = leray ? 1 : 0;
+        return s;
+    }
+
+    // -- per-velocity preparation ---------------------------------------------
+    // v^, R(v) (device scalar -> reg_cached), divergence, departure points and
+    // stationary source factors.
+    void prepare(const void* v, bool needY) {
+        const T* vin[3] = {comp(v, 0), comp(v, 1), d == 3 ? comp(v, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vh, d, st); });
+        run(KC_REDUCE, [&] {
+            return launch_spec_regvalue<double>(dm, specop(false), vh, partial, dres + 64, st);
+        });
+        if (delta) {
+            const double one = 1.0;
+            for (int cc = 0; cc < d; ++cc)
+                run(KC_DERIV, [&] {
+                    return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), comp(v, cc), 0,
+                                                nullptr, 0, &one, 1, cc > 0, delta, st);
+                });
+        }
+        run(KC_CHAR, [&] {
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, dX,
+                                             needY ? dY : nullptr, st);
+        });
+        y_valid = needY;
+        if (cfac)
+            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dX, ht, -1.0, cfac, st); });
+        if (bfac && needY)
+            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bfac, st); });
+    }
+
+    void ensure_Y(const void* v) {
+        if (y_valid) return;
+        // characteristics for -v only (the kernel needs a dX target; use tmp)
+        run(KC_CHAR, [&] {
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, tmp, dY, st);
+        });
+        if (bfac)
+            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bfac, st); });
+        y_valid = true;
+    }
+
+    void forward() {
+        for (int j = 0; j < cfg.nt; ++j)
+            run(KC_SL, [&] {
+                return launch_sl_step<T>(dm, mhist + j * N, dX, cfac, mhist + (j + 1) * N, st);
+            });
+    }
+
+    // mismatch sum -> dres[0]; optionally lam^nt = m1 - m^nt
+    void mismatch(bool write_lam) {
+        run(KC_REDUCE, [&] {
+            return launch_sumsq_diff<T>(mhist + cfg.nt * N, m1, write_lam ? lam + cfg.nt * N : nullptr,
+                                        N, partial, dres, st);
+        });
+    }
+
+    double finish_J(double* mis_out) {
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 128, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const double mis = 0.5 * cell * hres[0];
+        reg_cached = cell / double(N) * hres[64];
+        if (mis_out) *mis_out = mis;
+        return mis + 0.5 * cfg.alpha * reg_cached;
+    }
+
+    double objective(const void* v, bool keep, double* mis) override {
+        prepare(v, false);
+        forward();
+        mismatch(false);
+        fwd_valid = keep;
+        fwd_v = keep ? v : nullptr;
+        adj_valid = false;
+        return finish_J(mis);
+    }
+
+    double gradient(const void* v, void* g, bool reuse) override {
+        double J;
+        if (reuse) {
+            if (!fwd_valid || fwd_v != v)
+                throw Error(GANMRES_ESTATE, "reuse_forward without a kept forward solve for this v");
+            ensure_Y(v);
+            mismatch(true);
+            J = finish_J(nullptr);
+        } else {
+            prepare(v, true);
+            forward();
+            mismatch(true);
+            J = finish_J(nullptr);
+        }
+        // adjoint, backward in time
+        for (int j = cfg.nt - 1; j >= 0; --j)
+            run(KC_SL, [&] { return launch_sl_step<T>(dm, lam + (j + 1) * N, dY, bfac, lam + j * N, st); });
+        adj_valid = true;
+        // body force
+        std::vector<double> w(cfg.nt + 1, ht);
+        w[0] = w[cfg.nt] = 0.5 * ht;
+        const bool cont = cfg.model == GANMRES_CONTINUITY;
+        if (cont)
+            for (auto& x : w) x = -x;
+        for (int cc = 0; cc < d; ++cc)
+            run(KC_DERIV, [&] {
+                return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), cont ? lam : mhist, N,
+                                            cont ? mhist : lam, N, w.data(), cfg.nt + 1, 0,
+                                            comp(b, cc), st);
+            });
+        // assembly g = alpha L v + [P] b
+        const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
+        run(KC_SPEC, [&] {
+            return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vh, wh, wh, st);
+        });
+        T* gout[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / N, d, st); });
+        return J;
+    }
+
+    double precond(const void* g, void* s) override {
+        const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
+        run(KC_SPEC, [&] {
+            return launch_spec_precond<T>(dm, specop(cfg.incompressible != 0), wh, wh, st);
+        });
+        T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / N, d, st); });
+        run(KC_REDUCE, [&] {
+            return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), d * N, partial,
+                                 dres, st);
+        });
+        return cell * fetch();
+    }
+
+    double maxabs(const T* a) {
+        run(KC_REDUCE, [&] { return launch_maxabs<T>(a, d * N, partial, dres, st); });
+        return fetch();
+    }
+
+    void get_field(int which, int j, void* out) override {
+        if (j < 0 || j > cfg.nt || (which != 0 && which != 1))
+            throw Error(GANMRES_EINVAL, "field index out of range");
+        if (which == 1 && !adj_valid) throw Error(GANMRES_ESTATE, "no adjoint solve available");
+        const T* src = (which == 0 ? mhist : lam) + j * N;
+        HIPCHK(hipMemcpyAsync(out, src, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    // -- GA-NGMRES ----------------------------------------------------------
+    void reset() override {
+        started = false;
+        hist.clear();
+        k = 0;
+        rho_bar = 1.0;
+    }
+
+    T* rv(int slot) { return static_cast<T*>(ring_v[slot]->p); }
+    T* rg(int slot) { return static_cast<T*>(ring_g[slot]->p); }
+
+    void ensure_solver(int w) {
+        if (wcap == w) return;
+        if (started) throw Error(GANMRES_EINVAL, "window changed during a solve; reset first");
+        ring_v.clear();
+        ring_g.clear();
+        for (int i = 0; i < w + 2; ++i) {
+            ring_v.emplace_back(new DevBuf);
+            ring_v.back()->alloc(sizeof(T) * d * N);
+            ring_g.emplace_back(new DevBuf);
+            ring_g.back()->alloc(sizeof(T) * d * N);
+        }
+        qb.reset(new DevBuf);
+        qb->alloc(sizeof(T) * d * N);
+        gqb.reset(new DevBuf);
+        gqb->alloc(sizeof(T) * d * N);
+        sb.reset(new DevBuf);
+        sb->alloc(sizeof(T) * d * N);
+        wcap = w;
+    }
+
+    static bool is_fp(int k, const ganmres_solver_params& p) {
+        if (p.sigma == 0) return true;
+        const int m = k % (p.sigma + p.tau);
+        return p.variant == GANMRES_VARIANT_ALT ? (m < p.tau) : (m >= p.sigma);
+    }
+
+    void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) override {
+        ensure_solver(p.w);
+        info = ganmres_step_info{};
+        int ngrad = 0;
+        if (!started) {
+            HIPCHK(hipMemcpyAsync(rv(0), v, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+            Jcur = gradient(rv(0), rg(0), false);
+            ++ngrad;
+            g0inf = maxabs(rg(0));
+            if (!std::isfinite(Jcur) || !std::isfinite(g0inf))
+                throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient at v^0");
+            hist.assign(1, 0);
+            k = 0;
+            rho_bar = 1.0;
+            started = true;
+        }
+        const int cur = hist.back();
+        T* q = static_cast<T*>(qb->p);
+        T* gq = static_cast<T*>(gqb->p);
+        T* s = static_cast<T*>(sb->p);
+        // direction and line search (eqs. e:rpgd, e:armijo)
+        const double gs = precond(rg(cur), s);
+        double rho = rho_bar, Jq = 0.0;
+        int trials = 0;
+        bool accepted = false;
+        for (int t = 0; t <= p.max_backtracks; ++t) {
+            run(KC_VEC, [&] { return launch_axpy<T>(rv(cur), rho, s, q, d * N, st); });
+            Jq = objective(q, true, nullptr);
+            ++trials;
+            if (Jq < Jcur + p.c_armijo * rho * gs) {
+                rho_bar = (t == 0) ? 2.0 * rho : rho;
+                if (p.rho_cap > 0.0) rho_bar = std::min(rho_bar, p.rho_cap);
+                accepted = true;
+                break;
+            }
+            rho *= 0.5;
+        }
+        info.n_trials = trials;
+        if (!accepted) throw Error(GANMRES_ELINESEARCH, "Armijo condition not met");
+        const double Jq_grad = gradient(q, gq, true);
+        (void)Jq_grad;
+        ++ngrad;
+        // the free slot (not in the window)
+        int slot = -1;
+        for (int i = 0; i < (int)ring_v.size(); ++i)
+            if (std::find(hist.begin(), hist.end(), i) == hist.end()) {
+                slot = i;
+                break;
+            }
+        const bool fp = is_fp(k, p);
+        double Jnew;
+        if (fp) {
+            std::swap(ring_v[slot], qb);
+            std::swap(ring_g[slot], gqb);
+            Jnew = Jq;
+            info.step_kind = GANMRES_STEP_FP;
+        } else {
+            const int wk = std::min(k, p.w);
+            const int K = wk + 2;
+            std::vector<const T*> vecs(K);
+            vecs[0] = gq;
+            for (int i = 0; i <= wk; ++i) vecs[i + 1] = rg(hist[hist.size() - 1 - i]);
+            std::vector<double> G(K * K);
+            if (K <= 8) {
+                run(KC_REDUCE, [&] { return launch_gram<T>(vecs.data(), K, d * N, partial, dres, st); });
+                const int np = K * (K + 1) / 2;
+                HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                int qi = 0;
+                for (int a = 0; a < K; ++a)
+                    for (int bb = a; bb < K; ++bb) G[a * K + bb] = G[bb * K + a] = hres[qi++];
+            } else {
+                for (int a = 0; a < K; ++a)
+                    for (int bb = a; bb < K; ++bb) {
+                        run(KC_REDUCE, [&] { return launch_dot<T>(vecs[a], vecs[bb], d * N, partial, dres, st); });
+                        G[a * K + bb] = G[bb * K + a] = fetch();
+                    }
+            }
+            std::vector<double> beta = lsq_from_gram(K, G);
+            for (double x : beta)
+                if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
+            std::vector<const T*> xs(wk + 1);
+            for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
+            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), beta.data(), wk + 1, rv(slot), d * N, st); });
+            Jnew = gradient(rv(slot), rg(slot), false);
+            ++ngrad;
+            info.step_kind = GANMRES_STEP_NGMRES;
+            info.n_beta = wk + 1;
+            for (int i = 0; i <= wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = beta[i];
+        }
+        hist.push_back(slot);
+        while ((int)hist.size() > p.w + 1) hist.pop_front();
+        ++k;
+        const double ginf = maxabs(rg(slot));
+        Jcur = Jnew;
+        HIPCHK(hipMemcpyAsync(v, rv(slot), sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        info.k = k;
+        info.J = Jnew;
+        info.J_q = Jq;
+        info.ginf = ginf;
+        info.g0inf = g0inf;
+        info.rho = rho;
+        info.n_grad = ngrad;
+        info.stop = (ginf <= p.eps_rel * g0inf) || (k >= p.n_iter);
+        if (!std::isfinite(Jnew) || !std::isfinite(ginf))
+            throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient");
+    }
+};
+
+static bool size_ok(int n) {
+    if (n < 4 || n > 1024) return false;
+    int r[kMaxRadices];
+    return make_radices(n, r) > 0;
+}
+
+}  // namespace gan
+
+struct ganmres_handle {
+    std::unique_ptr<gan::ProblemBase> impl;
+    std::string err;
+    int dtype;
+};
+
+static thread_local std::string g_create_error;
+
+template <typename F>
+static int guarded(ganmres_handle* h, F&& f) {
+    try {
+        f();
+        if (h) h->err.clear();
+        return GANMRES_OK;
+    } catch (const gan::Error& e) {
+        if (h) h->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        if (h) h->err = "host allocation failed";
+        return GANMRES_ENOMEM;
+    } catch (...) {
+        if (h) h->err = "unexpected error";
+        return GANMRES_EDEVICE;
+    }
+}
+
+extern "C" {
+
+int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, void* stream,
+                   ganmres_handle** out) {
+    if (!cfg || !m0 || !m1 || !out) {
+        g_create_error = "null argument";
+        return GANMRES_EINVAL;
+    }
+    *out = nullptr;
+    const ganmres_config& c = *cfg;
+    std::string why;
+    if (c.dim != 2 && c.dim != 3) why = "dim must be 2 or 3";
+    for (int a = 0; a < c.dim && why.empty(); ++a)
+        if (!gan::size_ok(c.n[a])) why = "grid sizes must be 2^a 3^b in [4, 1024]";
+    if (why.empty() && c.nt < 1) why = "nt must be >= 1";
+    if (why.empty() && c.nt > 64) why = "nt must be <= 64";
+    if (why.empty() && !(c.alpha > 0.0)) why = "alpha must be > 0";
+    if (why.empty() && (c.reg_order < 1 || c.reg_order > 3)) why = "reg_order must be 1..3";
+    if (why.empty() && c.model != GANMRES_ADVECTION && c.model != GANMRES_CONTINUITY)
+        why = "unknown model";
+    if (why.empty() && c.dtype != GANMRES_F32 && c.dtype != GANMRES_F64) why = "unknown dtype";
+    if (why.empty() && c.incompressible && c.model == GANMRES_CONTINUITY)
+        why = "the incompressible option applies to the advection model";
+    if (why.empty() && c.checkpoint_every < 1) why = "checkpoint_every must be >= 1";
+    if (!why.empty()) {
+        g_create_error = why;
+        return GANMRES_EINVAL;
+    }
+    auto* h = new ganmres_handle;
+    h->dtype = c.dtype;
+    const int rc = guarded(h, [&] {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (c.dtype == GANMRES_F32) h->impl.reset(new gan::Problem<float>(c, m0, m1, st));
+        else h->impl.reset(new gan::Problem<double>(c, m0, m1, st));
+    });
+    if (rc != GANMRES_OK) {
+        g_create_error = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return GANMRES_OK;
+}
+
+int ganmres_destroy(ganmres_handle* h) {
+    delete h;
+    return GANMRES_OK;
+}
+
+const char* ganmres_last_error(const ganmres_handle* h) {
+    return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+int ganmres_eval_objective(ganmres_handle* h, const void* v, int keep_history, double* J,
+                           double* mismatch) {
+    if (!h || !v || !J) return GANMRES_EINVAL;
+    int rc = guarded(h, [&] { *J = h->impl->objective(v, keep_history != 0, mismatch); });
+    if (rc == GANMRES_OK && !std::isfinite(*J)) {
+        h->err = "non-finite objective";
+        rc = GANMRES_ENONFINITE;
+    }
+    return rc;
+}
+
+int ganmres_eval_gradient(ganmres_handle* h, const void* v, void* g, int reuse_forward, double* J) {
+    if (!h || !v || !g || v == g) {
+        if (h) h->err = "invalid arguments";
+        return GANMRES_EINVAL;
+    }
+    double Jv = 0.0;
+    int rc = guarded(h, [&] { Jv = h->impl->gradient(v, g, reuse_forward != 0); });
+    if (J) *J = Jv;
+    if (rc == GANMRES_OK && !std::isfinite(Jv)) {
+        h->err = "non-finite objective";
+        rc = GANMRES_ENONFINITE;
+    }
+    return rc;
+}
+
+int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs) {
+    if (!h || !g || !s) return GANMRES_EINVAL;
+    double x = 0.0;
+    const int rc = guarded(h, [&] { x = h->impl->precond(g, s); });
+    if (gs) *gs = x;
+    return rc;
+}
+
+int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
+                 ganmres_step_info* info) {
+    if (!h || !p || !v) return GANMRES_EINVAL;
+    if (p->w < 0 || p->w > GANMRES_MAX_WINDOW || p->sigma < 0 || p->tau < 0 ||
+        (p->sigma + p->tau) == 0 || p->n_iter < 1 || p->max_backtracks < 0) {
+        h->err = "invalid solver parameters";
+        return GANMRES_EINVAL;
+    }
+    ganmres_step_info local;
+    return guarded(h, [&] { h->impl->step(*p, v, info ? *info : local); });
+}
+
+int ganmres_solver_reset(ganmres_handle* h) {
+    if (!h) return GANMRES_EINVAL;
+    return guarded(h, [&] { h->impl->reset(); });
+}
+
+int ganmres_get_field(ganmres_handle* h, int which, int j, void* out) {
+    if (!h || !out) return GANMRES_EINVAL;
+    return guarded(h, [&] { h->impl->get_field(which, j, out); });
+}
+
+int ganmres_timing_enable(ganmres_handle* h, int on) {
+    if (!h) return GANMRES_EINVAL;
+    return guarded(h, [&] {
+        if (!on) h->impl->timing_flush();
+        h->impl->timing = on != 0;
+    });
+}
+
+int ganmres_timing_reset(ganmres_handle* h) {
+    if (!h) return GANMRES_EINVAL;
+    return guarded(h, [&] {
+        h->impl->timing_flush();
+        for (int i = 0; i < gan::KC_COUNT; ++i) {
+            h->impl->tms[i] = 0.0;
+            h->impl->tcount[i] = 0;
+        }
+    });
+}
+
+int ganmres_timing_get(ganmres_handle* h, int kernel, double* ms, long long* launches) {
+    if (!h || kernel < 0 || kernel >= gan::KC_COUNT) return GANMRES_EINVAL;
+    return guarded(h, [&] {
+        h->impl->timing_flush();
+        if (ms) *ms = h->impl->tms[kernel];
+        if (launches) *launches = h->impl->tcount[kernel];
+    });
+}
+
+int ganmres_kernel_count(void) { return gan::KC_COUNT; }
+
+const char* ganmres_kernel_name(int kernel) {
+    if (kernel < 0 || kernel >= gan::KC_COUNT) return "";
+    return gan::kKernelNames[kernel];
+}
+
+long long ganmres_workspace_bytes(const ganmres_handle* h) {
+    return h ? h->impl->workspace_bytes() : 0;
+}
+
+}  // extern "C"

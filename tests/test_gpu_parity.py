@@ -1,0 +1,171 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element.
+
+Tolerances (relative l2 unless stated): 1e-10 for the FP64 path, 1e-4 for
+the FP32 path, on the objective, the gradient, the terminal state, the adjoint
+at t = 0 and the preconditioned direction, at fixed probe velocities.
+Grids are chosen to span several LDS tiles with ragged tails (sizes that are
+not multiples of the tile widths, odd 3^b sizes).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import ngmres as ong
+from tests._cases import as_precision, oracle_problem, probes, rel, round_to
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-4}
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(x, dtype):
+    return torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+
+
+def host(t):
+    return t.detach().double().cpu().numpy()
+
+
+def make_gpu(P, wl, dtype):
+    import paper_2510_08782_amd as gan
+    return gan.Problem(dev(P.m0, dtype), dev(P.m1, dtype), P.nt, P.alpha, P.p, model=P.model,
+                       incompressible=P.incompressible)
+
+
+def check_probe(P, G, v, dtype, tol, name):
+    say(f"  probe {name}")
+    vd = dev(v, dtype)
+    Jg, mis = G.eval_objective(vd, with_mismatch=True)
+    Jo, miso, _ = P.objective(v, return_parts=True)
+    assert abs(Jg - Jo) <= tol * abs(Jo), (name, Jg, Jo)
+    assert abs(mis - miso) <= tol * max(abs(miso), 1e-300) + tol * abs(Jo), (name, mis, miso)
+    Jg2, g = G.eval_gradient(vd)
+    Jo2, go, st = P.gradient(v, return_states=True)
+    assert abs(Jg2 - Jo2) <= tol * abs(Jo2)
+    assert rel(host(G.get_field("state", P.nt)), st["m"][-1]) <= tol, name
+    lam_scale = max(np.abs(st["lam"][-1]).max(), 1e-300)
+    lam0 = host(G.get_field("adjoint", 0))
+    if np.abs(st["lam"][0]).max() > 0:
+        assert rel(lam0, st["lam"][0]) <= tol, name
+    else:
+        assert np.abs(lam0).max() <= tol * lam_scale
+    err = rel(host(g), go)
+    say(f"    J {Jg:.12e} / {Jo:.12e}  grad rel err {err:.3e}")
+    assert err <= tol, (name, err)
+    s, gs = G.apply_precond(g)
+    so, gso = ong.precond(P, go)
+    assert rel(host(s), so) <= tol, name
+    assert abs(gs - gso) <= 10 * tol * abs(gso), (gs, gso)
+
+
+CASES = [
+    # (workload, shape, nt)
+    ("c0", (48, 64), 4),
+    ("c1", (96, 72), 4),
+    ("c2", (24, 32, 48), 2),
+    ("c3", (32, 24, 36), 3),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_probe_parity(case, prec):
+    name, shape, nt = case
+    say(f"case {name} shape {shape} nt {nt} {prec}")
+    wl = synth.workload(name, shape=shape)
+    P = as_precision(oracle_problem(wl, nt=nt), prec)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    G = make_gpu(P, wl, dtype)
+    for pname, v in probes(wl).items():
+        check_probe(P, G, round_to(v, prec), dtype, TOL[prec], pname)
+    G.close()
+
+
+EDGE = [
+    ("odd27x36", "c0", (27, 36), 2, 1.0),
+    ("tiny4x6", "c0", (4, 6), 1, 1.0),
+    ("odd3d_9x12x27", "c3", (9, 12, 27), 1, 1.0),
+    ("big_displacement", "c0", (32, 48), 2, 12.0),
+    ("continuity_nt1", "c1", (16, 24), 1, 1.0),
+]
+
+
+@pytest.mark.parametrize("edge", EDGE, ids=[e[0] for e in EDGE])
+def test_edge_cases_f64(edge):
+    ename, name, shape, nt, vscale = edge
+    say(f"edge {ename} shape {shape} nt {nt} vscale {vscale}")
+    wl = synth.workload(name, shape=shape)
+    wl.vstar = wl.vstar * vscale
+    P = oracle_problem(wl, nt=nt)
+    G = make_gpu(P, wl, torch.float64)
+    for pname, v in probes(wl).items():
+        check_probe(P, G, v, torch.float64, TOL["f64"], pname)
+    G.close()
+
+
+def test_gradient_is_deterministic():
+    wl = synth.workload("c2", shape=(24, 32, 48))
+    P = oracle_problem(wl, nt=2)
+    G = make_gpu(P, wl, torch.float32)
+    v = dev(0.5 * wl.vstar, torch.float32)
+    _, g1 = G.eval_gradient(v)
+    _, g2 = G.eval_gradient(v)
+    J1 = G.eval_objective(v)
+    J2 = G.eval_objective(v)
+    assert torch.equal(g1, g2) and J1 == J2
+
+
+def test_reuse_forward_matches_fresh_gradient():
+    wl = synth.workload("c1", shape=(48, 64))
+    P = oracle_problem(wl, nt=3)
+    G = make_gpu(P, wl, torch.float64)
+    v = dev(0.5 * wl.vstar, torch.float64)
+    J0 = G.eval_objective(v, keep_history=True)
+    J1, g1 = G.eval_gradient(v, reuse_forward=True)
+    J2, g2 = G.eval_gradient(v)
+    assert J0 == J1 == J2
+    assert torch.equal(g1, g2)
+    import paper_2510_08782_amd as gan
+    G.eval_objective(v, keep_history=False)
+    with pytest.raises(gan.GanmresError) as ei:
+        G.eval_gradient(v, reuse_forward=True)
+    assert ei.value.code == -7
+
+
+def test_c0_trajectory_parity_f64():
+    """Config c0 (64^2, FP64, GA-NGMRES(5; 2, 1), 20 iterations) against the
+    oracle's loop: every iterate to 1e-8, J and the step kinds exactly."""
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c0")
+    P = oracle_problem(wl)
+    sv = wl.solver
+    res = ong.solve(P, w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                    n_iter=sv["n_iter"], keep_iterates=True)
+    G = make_gpu(P, wl, torch.float64)
+    params = gan.SolveParams(w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                             n_iter=sv["n_iter"])
+    v = G.new_velocity()
+    for k in range(1, sv["n_iter"] + 1):
+        info = G.step(params, v)
+        rec = res.records[k - 1]
+        err = rel(host(v), res.iterates[k])
+        say(f"  k {k} {('ngmres', 'fp')[info.step_kind]} J {info.J:.12e} / {rec.J:.12e} "
+            f"iterate err {err:.2e} trials {info.n_trials}/{rec.trials}")
+        assert ("ngmres", "fp")[info.step_kind] == rec.kind
+        assert info.n_trials == rec.trials
+        assert err <= 1e-8
+        assert abs(info.J - rec.J) <= 1e-10 * abs(rec.J)
+        if rec.beta is not None:
+            np.testing.assert_allclose(np.array(info.beta[:info.n_beta]), rec.beta, rtol=1e-6,
+                                       atol=1e-9)
+        if info.stop:
+            break
+    assert info.k == res.iterations

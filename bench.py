@@ -1,0 +1,262 @@
+"""Benchmark: gradient evaluations per second of GA-NGMRES on the 3-D 128^3
+incompressible advection workload (FP32 transport/FFT, FP64 Gram/LSQ), with
+the FP64 path, time-to-1e-2 gradient reduction, the roofline of the dominant
+kernel and the CPU oracle as a reported baseline.
+
+A step is one GA-NGMRES(5; 2, 1) iteration of the library (ganmres_step):
+preconditioner, Armijo line search (objective evaluations), gradient at q,
+Gram/least squares/update on NGMRES steps, stop test.  `value` counts the
+gradient evaluations those steps perform per second of wall time.
+Inputs (m0, m1, v) are resident in HBM before the timed region starts.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_problem(torch, gan, synth, dtype, wl):
+    """Device problem of workload wl; m1 = m0 transported by v* with the
+    library's own forward solve (the benchmark's reference image)."""
+    dev = lambda x: torch.tensor(x, dtype=dtype, device="cuda")
+    m0 = dev(wl.m0)
+    vstar = dev(wl.vstar)
+    gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, model=wl.model,
+                      incompressible=wl.incompressible)
+    gen.eval_objective(vstar)
+    m1 = gen.get_field("state", wl.nt)
+    gen.close()
+    P = gan.Problem(m0, m1, wl.nt, wl.alpha, wl.reg_order, model=wl.model,
+                    incompressible=wl.incompressible)
+    return P, vstar
+
+
+def run_steps(torch, P, params, v, nsteps):
+    """nsteps GA-NGMRES iterations (restarting from v = 0 after a stop).
+    Returns (gradient evaluations, objective evaluations)."""
+    ngrad = nobj = 0
+    for _ in range(nsteps):
+        info = P.step(params, v)
+        ngrad += info.n_grad
+        nobj += info.n_trials
+        if info.stop:
+            P.reset()
+            v.zero_()
+    return ngrad, nobj
+
+
+def time_steps(torch, P, params, steps, warmup, timing=False):
+    v = P.new_velocity()
+    P.reset()
+    run_steps(torch, P, params, v, warmup)
+    if timing:
+        P.timing(True)
+        P.timing_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ngrad, nobj = run_steps(torch, P, params, v, steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rep = None
+    if timing:
+        rep = P.timing_report()
+        P.timing(False)
+    return t1 - t0, ngrad, nobj, rep
+
+
+def time_gradients(torch, P, v, reps):
+    g = P.new_velocity()
+    P.eval_gradient(v, g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.eval_gradient(v, g)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def time_to_solution(torch, P, params):
+    v = P.new_velocity()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    v, infos = P.solve(params, v0=v)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    last = infos[-1]
+    return dict(seconds=round(t, 4), iterations=last.k,
+                rel_grad=last.ginf / last.g0inf, reached=bool(last.ginf <= params.eps_rel * last.g0inf),
+                grad_evals=sum(i.n_grad for i in infos) + 1,
+                obj_evals=sum(i.n_trials for i in infos), J=last.J)
+
+
+def algorithmic_bytes(kernel, wl, N, s):
+    """Compulsory HBM bytes of one launch of `kernel` on this workload.
+
+    sl_step:    read source field, d displacement fields (plus the factor
+                when a source term is present), write one field.
+    deriv_axis: body force along one axis: read (n_t+1) states and (n_t+1)
+                adjoints, write one component.
+    """
+    d = len(wl.shape)
+    if kernel == "sl_step":
+        return (1 + d + 1) * N * s
+    if kernel == "deriv_axis":
+        return (2 * (wl.nt + 1) + 1) * N * s
+    return None
+
+
+def cpu_baseline(synth_mod):
+    """The FP64 oracle's gradient on the same recipe at 64^3 (1/8 of the
+    points), scaled to the 128^3 workload by the point count."""
+    import numpy as np
+    from oracle.transport import TransportProblem
+    wl = synth_mod.workload("c2", shape=(64, 64, 64))
+    gen = TransportProblem(wl.m0, wl.m0, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
+    m1 = gen.forward(wl.vstar)[-1]
+    P = TransportProblem(wl.m0, m1, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
+    v = 0.5 * wl.vstar
+    t0 = time.perf_counter()
+    P.gradient(v)
+    t = time.perf_counter() - t0
+    scale = (128 ** 3) / (64 ** 3)
+    return {"value": round(1.0 / (t * scale), 6), "unit": "grad evals/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"one oracle gradient of the 128^3 recipe at 64^3 ({t:.1f} s, numpy, "
+                      f"single thread), time scaled x{scale:.0f} by grid points"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                                   "(see the sharding notes in DESIGN.md)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2510_08782_amd as gan
+    import synth
+
+    wl = synth.workload("c2")
+    N = int(np.prod(wl.shape))
+    sv = wl.solver
+    params = gan.SolveParams(w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                             n_iter=sv["n_iter"])
+    log(f"workload c2 {wl.shape} nt={wl.nt}; building FP32 problem")
+    P32, vstar32 = make_problem(torch, gan, synth, torch.float32, wl)
+
+    if args.copy_probe:
+        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    log(f"timing {args.steps} FP32 steps after {args.warmup} warmup")
+    dt, ngrad, nobj, rep = time_steps(torch, P32, params, args.steps, args.warmup, timing=True)
+    value = ngrad / dt
+    log(f"FP32: {ngrad} grads in {dt:.3f}s -> {value:.1f} grad/s ; kernels {rep}")
+
+    # dominant kernel of the timed region and its roofline
+    dom = max(rep.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dcount) = dom
+    bpl = algorithmic_bytes(dname, wl, N, 4)
+    roofline = None
+    if bpl is not None and dcount > 0:
+        avg_ms = dms / dcount
+        achieved = bpl / (avg_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "bytes_per_launch": bpl, "launches": dcount}
+    kernels = {k: {"ms": round(ms, 3), "launches": c,
+                   "avg_us": round(1e3 * ms / c, 2) if c else None,
+                   "share": round(ms / max(sum(x[0] for x in rep.values()), 1e-12), 4)}
+               for k, (ms, c) in rep.items()}
+    for kname in ("sl_step", "deriv_axis"):
+        b = algorithmic_bytes(kname, wl, N, 4)
+        if kname in rep and rep[kname][1]:
+            kernels[kname]["GBps"] = round(b / (rep[kname][0] / rep[kname][1] * 1e-3) / 1e9, 1)
+
+    extra = {}
+    v_half = (0.5 * vstar32).contiguous()
+    extra["grad_eval_only_fp32_per_s"] = round(1.0 / time_gradients(torch, P32, v_half, 10), 2)
+    if not args.no_tts:
+        log("time-to-1e-2, FP32 GA-NGMRES")
+        extra["tts_fp32_ga_ngmres"] = time_to_solution(torch, P32, params)
+    extra["peak_workspace_bytes_fp32"] = P32.workspace_bytes()
+    P32.close()
+
+    if not args.no_fp64:
+        log("FP64 path")
+        P64, vstar64 = make_problem(torch, gan, synth, torch.float64, wl)
+        k64 = max(4, args.steps // 3)
+        dt64, ng64, _, _ = time_steps(torch, P64, params, k64, 2)
+        extra["fp64_grad_evals_per_s"] = round(ng64 / dt64, 2)
+        extra["grad_eval_only_fp64_per_s"] = round(
+            1.0 / time_gradients(torch, P64, (0.5 * vstar64).contiguous(), 5), 2)
+        if not args.no_tts:
+            log("time-to-1e-2, FP64 GA-NGMRES")
+            extra["tts_fp64_ga_ngmres"] = time_to_solution(torch, P64, params)
+        P64.close()
+
+    cpu = None
+    if not args.no_cpu:
+        log("CPU oracle sample")
+        cpu = cpu_baseline(synth)
+
+    out = {
+        "metric": "grad evals/sec at 3D 128^3 (FP32 vs FP64), time-to-1e-2 grad reduction",
+        "value": round(value, 2),
+        "unit": "grad evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(1e3 * dt / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2: 3-D incompressible advection 128^3, nt=4, H1, alpha=1e-4, "
+                               "GA-NGMRES(5;2,1), FP32 transport/FFT, FP64 Gram/LSQ",
+                   "grid": list(wl.shape), "nt": wl.nt, "grad_evals_timed": ngrad,
+                   "obj_evals_timed": nobj},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels_fp32": kernels,
+        **extra,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -103,14 +103,17 @@ __host__ __device__ inline void stockham_dispatch(int R, const C2<T>* in, C2<T>*
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // Whole transform of the PC pencils held in LDS buffer a (b is scratch of the
 // same size).  Returns the buffer holding the result.  Ends with a barrier.
+// tw: the twiddle table (typically a copy in LDS); the plan's radices stay in
+// the kernel arguments.
 template <typename T>
-__device__ inline C2<T>* block_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, int pcshift, int dir) {
+__device__ inline C2<T>* block_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, const C2<T>* tw,
+                                   int pcshift, int dir) {
     int Ns = 1;
     for (int s = 0; s < pl.nrad; ++s) {
         const int R = pl.rad[s];
         const int nbt = (pl.L / R) << pcshift;
         for (int t = threadIdx.x; t < nbt; t += blockDim.x)
-            stockham_dispatch<T>(R, a, b, t, pl.L, pcshift, Ns, pl.tw, dir);
+            stockham_dispatch<T>(R, a, b, t, pl.L, pcshift, Ns, tw, dir);
         __syncthreads();
         C2<T>* tmp = a;
         a = b;

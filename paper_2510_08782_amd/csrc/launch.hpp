@@ -7,19 +7,29 @@
 namespace gan {
 
 // ---- semi-Lagrangian kernels (sl.hip) --------------------------------------
-// RK2 departure displacements (index units) for velocity +v (dX) and -v (dY,
-// nullable).  s[c] = h_t / h_c converts component c to cells per step.
+// Displacement bounds are device ints: ceil(max |d|) of a displacement field.
+// bounds[0]: state departure dX, bounds[1]: adjoint departure dY,
+// bounds[2]: predictor (max |u|).  The gathers read them to pick the LDS path.
 template <typename T>
-hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, T* dX, T* dY,
-                                  hipStream_t st);
-// out = [fac *] I[src](i + disp)
+hipError_t launch_zero_bounds(int* bounds, int n, hipStream_t st);
+// bounds_u = ceil(max_c max_i |s_c v_c(i)|)  (accumulated with atomicMax)
 template <typename T>
-hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, T* out,
-                          hipStream_t st);
+hipError_t launch_velocity_bound(const Dims& dm, const T* v, const double* s, int* bound_u,
+                                 hipStream_t st);
+// RK2 departure displacements (index units) for velocity +v (dX, nullable) and
+// -v (dY, nullable).  s[c] = h_t / h_c converts component c to cells per step.
+// Accumulates the bounds of dX / dY into bound_out[0] / bound_out[1].
+template <typename T>
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, const int* ubound,
+                                  T* dX, T* dY, int* bound_out, hipStream_t st);
+// out = [fac *] I[src](i + disp); `bound` is the bound of disp
+template <typename T>
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac,
+                          const int* bound, T* out, hipStream_t st);
 // out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, T* out, hipStream_t st);
+                                double sgn, const int* bound, T* out, hipStream_t st);
 
 // ---- reductions and vector kernels (vec.hip) -------------------------------
 // Deterministic two-stage FP64 reductions; the result lands in res[0] (device).

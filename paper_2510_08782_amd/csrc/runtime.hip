@@ -220,6 +220,7 @@ class Problem : public ProblemBase {
     C2<double>* vh[3];
     CT* wh[3];
     double *partial, *dres;
+    int* bounds;  // device: [0] dX, [1] dY, [2] predictor
     double* hres;  // pinned host results
     long long ws_bytes = 0;
     bool fwd_valid = false;
@@ -331,6 +332,9 @@ class Problem : public ProblemBase {
             bufs.emplace_back(new DevBuf);
             bufs.back()->alloc(sizeof(double) * 128);
             dres = static_cast<double*>(bufs.back()->p);
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(int) * 8);
+            bounds = static_cast<int*>(bufs.back()->p);
         }
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 128, hipHostMallocDefault));
         HIPCHK(hipMemcpyAsync(m0, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
@@ -429,31 +433,42 @@ class Problem : public ProblemBase {
                 });
         }
         run(KC_CHAR, [&] {
-            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, dX,
-                                             needY ? dY : nullptr, st);
+            HIPCHK(launch_zero_bounds<T>(bounds, 3, st));
+            HIPCHK(launch_velocity_bound<T>(dm, static_cast<const T*>(v), cscale, bounds + 2, st));
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, bounds + 2, dX,
+                                             needY ? dY : nullptr, bounds, st);
         });
         y_valid = needY;
         if (cfac)
-            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dX, ht, -1.0, cfac, st); });
+            run(KC_FACTOR, [&] {
+                return launch_source_factor<T>(dm, delta, dX, ht, -1.0, bounds + 0, cfac, st);
+            });
         if (bfac && needY)
-            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bfac, st); });
+            run(KC_FACTOR, [&] {
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bounds + 1, bfac, st);
+            });
     }
 
     void ensure_Y(const void* v) {
         if (y_valid) return;
-        // characteristics for -v only (the kernel needs a dX target; use tmp)
+        // characteristics for -v only; the predictor bound of v is still current
         run(KC_CHAR, [&] {
-            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, tmp, dY, st);
+            HIPCHK(launch_zero_bounds<T>(bounds + 1, 1, st));
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, bounds + 2,
+                                             nullptr, dY, bounds, st);
         });
         if (bfac)
-            run(KC_FACTOR, [&] { return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bfac, st); });
+            run(KC_FACTOR, [&] {
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bounds + 1, bfac, st);
+            });
         y_valid = true;
     }
 
     void forward() {
         for (int j = 0; j < cfg.nt; ++j)
             run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, mhist + j * N, dX, cfac, mhist + (j + 1) * N, st);
+                return launch_sl_step<T>(dm, mhist + j * N, dX, cfac, bounds + 0,
+                                         mhist + (j + 1) * N, st);
             });
     }
 
@@ -500,7 +515,9 @@ class Problem : public ProblemBase {
         }
         // adjoint, backward in time
         for (int j = cfg.nt - 1; j >= 0; --j)
-            run(KC_SL, [&] { return launch_sl_step<T>(dm, lam + (j + 1) * N, dY, bfac, lam + j * N, st); });
+            run(KC_SL, [&] {
+                return launch_sl_step<T>(dm, lam + (j + 1) * N, dY, bfac, bounds + 1, lam + j * N, st);
+            });
         adj_valid = true;
         // body force
         std::vector<double> w(cfg.nt + 1, ht);

@@ -26,62 +26,61 @@ extern __shared__ double2 gan_smem[];
 namespace {
 
 constexpr int kFftThreads = 256;
-constexpr int kMaxItems = 16;       // tile elements per thread (2 PC L <= 4096)
+constexpr int kItems = 8;           // tile elements per thread (tile <= 2048 elements)
 constexpr int kMaxTime = 65;
+constexpr int kLdsBudget = 64 * 1024;
 
-// log2 of the number of complex pencils per tile for pencils of length L.
-// Real-pencil tiles hold 2 PC L <= kFftThreads * kMaxItems elements.
-int pc_shift_for(int L, int bytes_per_complex, int max_pencils) {
+// log2 of the complex pencils per tile for kernels whose tile holds 2 PC real
+// pencils of length L (2 PC L <= kFftThreads * kItems), with two complex LDS
+// buffers and the twiddle table within the LDS budget.
+int pc_shift_real(int L, int bytes_per_complex, long long npencils) {
     int s = 0;
-    while ((2 << (s + 1)) * L <= kFftThreads * kMaxItems && (2 << s) < max_pencils &&
-           (1 << (s + 1)) * L * bytes_per_complex * 2 <= 64 * 1024 && s < 5)
+    while ((2 << (s + 1)) * L <= kFftThreads * kItems && (2LL << s) < npencils &&
+           (2 * (1 << (s + 1)) + 1) * L * bytes_per_complex <= kLdsBudget && s < 5)
         ++s;
     return s;
 }
-
-// log2 of the number of complex pencils per tile of the in-place complex
-// transforms (no per-thread accumulators): two LDS buffers within 64 KB.
-int pc_shift_c2c(int L, int bytes_per_complex, int ncols) {
+// Same for in-place complex transforms: tiles of PC complex pencils.
+int pc_shift_cplx(int L, int bytes_per_complex, long long npencils) {
     int s = 0;
-    while ((2 << s) <= ncols && (2 << s) * L * bytes_per_complex * 2 <= 64 * 1024 && s < 5) ++s;
+    while ((1 << (s + 1)) * L <= kFftThreads * kItems && (1LL << s) < npencils &&
+           (2 * (1 << (s + 1)) + 1) * L * bytes_per_complex <= kLdsBudget && s < 5)
+        ++s;
     return s;
 }
-
-// Geometry of a tile of real pencils along `axis`.
-struct RealTile {
-    long long base;  // element offset of pencil 0, position 0
-    int pstride;     // between pencils of the tile
-    int estride;     // between positions along the pencil
-    int valid;       // pencils of the tile inside the array
-};
-
-__device__ inline RealTile real_tile(const Dims& dm, int axis, int npen, int t) {
-    RealTile rt;
-    const int n0 = dm.n[0], n1 = dm.n[1], n2 = dm.n[2];
-    if (axis == 2) {
-        const long long q0 = (long long)t * npen;
-        const long long rows = (long long)n0 * n1;
-        rt.base = q0 * n2;
-        rt.pstride = n2;
-        rt.estride = 1;
-        rt.valid = (int)((rows - q0) < npen ? (rows - q0) : npen);
-    } else {
-        const int nch = (n2 + npen - 1) / npen;
-        const int outer = t / nch, ch = t % nch;
-        rt.base = (axis == 1 ? (long long)outer * n1 * n2 : (long long)outer * n2) +
-                  (long long)ch * npen;
-        rt.pstride = 1;
-        rt.estride = axis == 1 ? n2 : n1 * n2;
-        rt.valid = (n2 - ch * npen) < npen ? (n2 - ch * npen) : npen;
-    }
-    return rt;
+size_t fft_lds_bytes(int PC, int L, int bytes_per_complex) {
+    return (size_t)(2 * PC + 1) * L * bytes_per_complex;
 }
 
-// Element q of a real tile (2 PC pencils x L): pencil r and position i.
-__device__ inline void tile_item(const RealTile& rt, int q, int L, int pcshift, int& r, int& i) {
-    if (rt.pstride == 1) {
-        r = q & ((2 << pcshift) - 1);
-        i = q >> (pcshift + 1);
+// Pencils along `axis` of an (n0, n1, w) array (w = n2 for real data, n2/2+1
+// for the half spectrum), numbered p = 0..count-1 so that consecutive pencils
+// of the strided axes are adjacent in memory.
+__host__ __device__ inline long long pencil_count(const Dims& dm, int axis, int w) {
+    return axis == 2 ? (long long)dm.n[0] * dm.n[1]
+                     : (axis == 1 ? (long long)dm.n[0] * w : (long long)dm.n[1] * w);
+}
+__device__ inline long long pencil_base(const Dims& dm, int axis, int w, long long p) {
+    if (axis == 2) return p * w;
+    if (axis == 1) return (p / w) * dm.n[1] * w + p % w;
+    return p;
+}
+__device__ inline long long pencil_stride(const Dims& dm, int axis, int w) {
+    return axis == 2 ? 1 : (axis == 1 ? w : (long long)dm.n[1] * w);
+}
+
+template <typename T>
+__device__ inline C2<T>* twiddles_to_lds(const FftPlan<T>& pl, C2<T>* tws) {
+    for (int m = threadIdx.x; m < pl.L; m += kFftThreads) tws[m] = pl.tw[m];
+    return tws;
+}
+
+// Item e of a tile of NP real pencils x L: its pencil r and position i.
+// Strided axes put the pencil index fastest (coalesced over adjacent
+// pencils); the contiguous axis puts the position fastest.
+__device__ inline void item_pos(int axis, int q, int L, int npshift, int& r, int& i) {
+    if (axis != 2) {
+        r = q & ((1 << npshift) - 1);
+        i = q >> npshift;
     } else {
         r = q / L;
         i = q - r * L;
@@ -104,65 +103,76 @@ struct DerivArgs {
 };
 
 // out = [out +] sum_t w_t G_t d/dx_axis F_t over one tile of 2 PC real pencils.
+// The loads of G_t and F_{t+1} are issued before the transforms of step t so
+// that they complete while the LDS passes run.
 template <typename T>
 __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a) {
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
     const int L = a.pl.L;
     const int PC = 1 << a.pcshift;
+    const int npshift = a.pcshift + 1;
+    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
     C2<T>* bufB = bufA + PC * L;
-    const RealTile rt = real_tile(a.dm, a.axis, 2 * PC, blockIdx.x);
-    const int nitems = 2 * PC * L;
+    const FftPlan<T>& pl = a.pl;
+    const C2<T>* tw = twiddles_to_lds(a.pl, bufB + PC * L);
+    const Dims& dm = a.dm;
+    const long long npen = pencil_count(dm, a.axis, dm.n[2]);
+    const long long stride = pencil_stride(dm, a.axis, dm.n[2]);
+    const long long p0 = (long long)blockIdx.x << npshift;
+    const int nitems = (2 * PC) * L;
     const T inv_l = T(1) / T(L);
 
-    T acc[kMaxItems];
-    long long addr[kMaxItems];
-    bool ok[kMaxItems];
+    long long off[kItems];
+    int slot[kItems];  // T index in bufA: 2 * complex index + (0 real | 1 imag); -1: no item
+    bool ok[kItems];
+    T acc[kItems], fv[kItems], gv[kItems];
 #pragma unroll
-    for (int e = 0; e < kMaxItems; ++e) {
+    for (int e = 0; e < kItems; ++e) {
         const int q = threadIdx.x + e * kFftThreads;
-        int r = 0, i = 0;
-        if (q < nitems) tile_item(rt, q, L, a.pcshift, r, i);
-        ok[e] = q < nitems && r < rt.valid;
-        addr[e] = rt.base + (long long)r * rt.pstride + (long long)i * rt.estride;
-        acc[e] = (ok[e] && a.accumulate) ? a.out[addr[e]] : T(0);
-    }
-    for (int t = 0; t < a.ntime; ++t) {
-        const T* F = a.F + t * a.fstride;
-#pragma unroll
-        for (int e = 0; e < kMaxItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q >= nitems) break;
+        slot[e] = -1;
+        ok[e] = false;
+        off[e] = 0;
+        if (q < nitems) {
             int r, i;
-            tile_item(rt, q, L, a.pcshift, r, i);
-            const T val = ok[e] ? F[addr[e]] : T(0);
-            T* slot = reinterpret_cast<T*>(&bufA[(i << a.pcshift) + (r & (PC - 1))]);
-            slot[r >> a.pcshift] = val;
+            item_pos(a.axis, q, L, npshift, r, i);
+            slot[e] = 2 * ((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
+            ok[e] = p0 + r < npen;
+            if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
         }
+        acc[e] = (ok[e] && a.accumulate) ? a.out[off[e]] : T(0);
+        fv[e] = ok[e] ? a.F[off[e]] : T(0);
+        gv[e] = T(1);
+    }
+    T* flat = reinterpret_cast<T*>(bufA);
+    for (int t = 0; t < a.ntime; ++t) {
+#pragma unroll
+        for (int e = 0; e < kItems; ++e)
+            if (slot[e] >= 0) flat[slot[e]] = fv[e];
         __syncthreads();
-        C2<T>* X = block_fft<T>(bufA, bufB, a.pl, a.pcshift, -1);
+        const T* G = a.G ? a.G + t * a.gstride : nullptr;
+        const T* Fn = a.F + (t + 1) * a.fstride;
+        const bool more = t + 1 < a.ntime;
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
+            if (more) fv[e] = ok[e] ? Fn[off[e]] : T(0);
+        }
+        C2<T>* X = block_fft<T>(bufA, bufB, pl, tw, a.pcshift, -1);
         for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
             const int i = q >> a.pcshift;
             X[q] = cmuli(X[q], T(wavenumber_odd(i, L)) * inv_l);
         }
         __syncthreads();
-        C2<T>* Y = block_fft<T>(X, X == bufA ? bufB : bufA, a.pl, a.pcshift, +1);
-        const T* G = a.G ? a.G + t * a.gstride : nullptr;
+        const C2<T>* Y = block_fft<T>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
+        const T* yflat = reinterpret_cast<const T*>(Y);
         const T wt = T(a.w[t]);
 #pragma unroll
-        for (int e = 0; e < kMaxItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q >= nitems) break;
-            int r, i;
-            tile_item(rt, q, L, a.pcshift, r, i);
-            const C2<T> z = Y[(i << a.pcshift) + (r & (PC - 1))];
-            const T d = (r >> a.pcshift) ? z.y : z.x;
-            if (ok[e]) acc[e] += wt * (G ? G[addr[e]] : T(1)) * d;
-        }
+        for (int e = 0; e < kItems; ++e)
+            if (ok[e]) acc[e] += wt * gv[e] * yflat[slot[e]];
         __syncthreads();
     }
 #pragma unroll
-    for (int e = 0; e < kMaxItems; ++e)
-        if (ok[e]) a.out[addr[e]] = acc[e];
+    for (int e = 0; e < kItems; ++e)
+        if (ok[e]) a.out[off[e]] = acc[e];
 }
 
 template <typename T>
@@ -182,29 +192,42 @@ struct OutPtrs {
 // Real rows (axis 2) of type TI -> half-spectrum rows computed and stored in
 // precision TC, for field blockIdx.y.
 template <typename TI, typename TC>
-__global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<TC> pl, int pcshift,
+__global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<TC> pl0, int pcshift,
                                                                InPtrs<TI> ip, SpecPtrs<TC> sp) {
     using T = TC;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    const int L = pl.L;
+    const int L = pl0.L;
     const int PC = 1 << pcshift;
+    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
     C2<T>* bufB = bufA + PC * L;
+    const FftPlan<T>& pl = pl0;
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
     const TI* in = ip.in[blockIdx.y];
     C2<T>* spec = sp.spec[blockIdx.y];
-    const RealTile rt = real_tile(dm, 2, 2 * PC, blockIdx.x);
+    const long long rows = (long long)dm.n[0] * dm.n[1];
     const long long q0 = (long long)blockIdx.x * 2 * PC;
-    for (int q = threadIdx.x; q < 2 * PC * L; q += kFftThreads) {
+    const int nitems = 2 * PC * L;
+    T vals[kItems];
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
         const int r = q / L, i = q - r * L;
-        const T val = r < rt.valid ? T(in[rt.base + (long long)r * L + i]) : T(0);
-        T* slot = reinterpret_cast<T*>(&bufA[(i << pcshift) + (r & (PC - 1))]);
-        slot[r >> pcshift] = val;
+        vals[e] = (q < nitems && q0 + r < rows) ? T(in[(q0 + r) * L + i]) : T(0);
+    }
+    T* flat = reinterpret_cast<T*>(bufA);
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        if (q < nitems) {
+            const int r = q / L, i = q - r * L;
+            flat[2 * ((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+        }
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, pcshift, -1);
+    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, -1);
     const int nh = dm.n2h;
     for (int q = threadIdx.x; q < 2 * PC * nh; q += kFftThreads) {
         const int r = q / nh, k = q - r * nh;
-        if (r >= rt.valid) continue;
+        if (q0 + r >= rows) continue;
         const int p = r & (PC - 1);
         const C2<T> zk = Z[(k << pcshift) + p];
         const int km = k == 0 ? 0 : L - k;
@@ -216,77 +239,110 @@ __global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<
     }
 }
 
-// In-place complex transform of the half spectrum along axis 0 or 1.
+// In-place complex transform of the half spectrum along axis 0 or 1, on tiles
+// of PC adjacent pencils.
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<T> pl, int axis,
+__global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<T> pl0, int axis,
                                                                int pcshift, int dir,
                                                                SpecPtrs<T> sp) {
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    const int L = pl.L;
+    const int L = pl0.L;
     const int PC = 1 << pcshift;
+    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
     C2<T>* bufB = bufA + PC * L;
+    const FftPlan<T>& pl = pl0;
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
     C2<T>* spec = sp.spec[blockIdx.y];
     const int nh = dm.n2h;
-    const int nch = (nh + PC - 1) / PC;
-    const int outer = blockIdx.x / nch, ch = blockIdx.x % nch;
-    const long long base = (axis == 1 ? (long long)outer * dm.n[1] * nh : (long long)outer * nh) +
-                           (long long)ch * PC;
-    const long long es = axis == 1 ? nh : (long long)dm.n[1] * nh;
-    const int valid = (nh - ch * PC) < PC ? (nh - ch * PC) : PC;
-    for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
-        const int p = q & (PC - 1), i = q >> pcshift;
-        bufA[q] = p < valid ? spec[base + p + i * es] : cmk(T(0), T(0));
+    const long long npen = pencil_count(dm, axis, nh);
+    const long long stride = pencil_stride(dm, axis, nh);
+    const long long p0 = (long long)blockIdx.x << pcshift;
+    const int pl_ = threadIdx.x & (PC - 1);
+    const bool ok = p0 + pl_ < npen;
+    const long long base = ok ? pencil_base(dm, axis, nh, p0 + pl_) : 0;
+    const int nitems = PC * L;
+    C2<T> vals[kItems];
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        const int i = q >> pcshift;
+        vals[e] = (q < nitems && ok) ? spec[base + i * stride] : cmk(T(0), T(0));
+    }
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        if (q < nitems) bufA[q] = vals[e];
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, pcshift, dir);
-    for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
-        const int p = q & (PC - 1), i = q >> pcshift;
-        if (p < valid) spec[base + p + i * es] = Z[q];
+    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, dir);
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[q];
     }
 }
 
 // Half-spectrum rows -> real rows: out = scale * x [+ add].
 template <typename T>
-__global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<T> pl, int pcshift,
+__global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<T> pl0, int pcshift,
                                                                T scale, SpecPtrs<T> sp,
                                                                OutPtrs<T> op) {
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    const int L = pl.L;
+    const int L = pl0.L;
     const int PC = 1 << pcshift;
+    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
     C2<T>* bufB = bufA + PC * L;
+    const FftPlan<T>& pl = pl0;
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
     const C2<T>* spec = sp.spec[blockIdx.y];
     T* out = op.out[blockIdx.y];
     const T* add = op.add[blockIdx.y];
-    const RealTile rt = real_tile(dm, 2, 2 * PC, blockIdx.x);
+    const long long rows = (long long)dm.n[0] * dm.n[1];
     const long long q0 = (long long)blockIdx.x * 2 * PC;
     const int nh = dm.n2h;
-    for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
+    const int nitems = PC * L;
+    constexpr int EH = kItems / 2;  // PC L <= kFftThreads * kItems / 2
+    C2<T> A[EH], B[EH];
+#pragma unroll
+    for (int e = 0; e < EH; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        const int p = q / L, i = q - p * L;
+        const int ks = 2 * i > L ? L - i : i;
+        A[e] = (q < nitems && q0 + p < rows) ? spec[(q0 + p) * nh + ks] : cmk(T(0), T(0));
+        B[e] = (q < nitems && q0 + p + PC < rows) ? spec[(q0 + p + PC) * nh + ks] : cmk(T(0), T(0));
+    }
+#pragma unroll
+    for (int e = 0; e < EH; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        if (q >= nitems) continue;
         const int p = q / L, i = q - p * L;
         const bool upper = 2 * i > L;
         const int ks = upper ? L - i : i;
-        C2<T> A = cmk(T(0), T(0)), B = cmk(T(0), T(0));
-        if (p < rt.valid) A = spec[(q0 + p) * nh + ks];
-        if (p + PC < rt.valid) B = spec[(q0 + p + PC) * nh + ks];
+        C2<T> a = A[e], b = B[e];
         if (ks == 0 || 2 * ks == L) {
-            A.y = T(0);
-            B.y = T(0);
+            a.y = T(0);
+            b.y = T(0);
         }
         if (upper) {
-            A.y = -A.y;
-            B.y = -B.y;
+            a.y = -a.y;
+            b.y = -b.y;
         }
-        bufA[(i << pcshift) + p] = cmk(A.x - B.y, A.y + B.x);
+        bufA[(i << pcshift) + p] = cmk(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, pcshift, +1);
-    for (int q = threadIdx.x; q < 2 * PC * L; q += kFftThreads) {
+    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, +1);
+    T addv[kItems];
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
         const int r = q / L, i = q - r * L;
-        if (r >= rt.valid) continue;
+        addv[e] = (add && q < 2 * nitems && q0 + r < rows) ? add[(q0 + r) * L + i] : T(0);
+    }
+#pragma unroll
+    for (int e = 0; e < kItems; ++e) {
+        const int q = threadIdx.x + e * kFftThreads;
+        const int r = q / L, i = q - r * L;
+        if (q >= 2 * nitems || q0 + r >= rows) continue;
         const C2<T> z = Z[(i << pcshift) + (r & (PC - 1))];
-        const long long o = rt.base + (long long)r * L + i;
-        T val = scale * ((r >> pcshift) ? z.y : z.x);
-        if (add) val += add[o];
-        out[o] = val;
+        out[(q0 + r) * L + i] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e];
     }
 }
 
@@ -404,13 +460,6 @@ inline int pointwise_blocks(long long n) {
     return (int)(b < 1 ? 1 : b);
 }
 
-template <typename T>
-int real_tiles(const Dims& dm, int axis, int npen) {
-    if (axis == 2) return (int)(((long long)dm.n[0] * dm.n[1] + npen - 1) / npen);
-    const int nch = (dm.n[2] + npen - 1) / npen;
-    return (axis == 1 ? dm.n[0] : dm.n[1]) * nch;
-}
-
 }  // namespace
 
 template <typename T>
@@ -423,8 +472,8 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     a.pl = pl.p[axis];
     a.axis = axis;
     const int L = dm.n[axis];
-    const int pencils = axis == 2 ? dm.n[0] * dm.n[1] : dm.n[2];
-    a.pcshift = pc_shift_for(L, (int)sizeof(C2<T>), pencils);
+    const long long npen = pencil_count(dm, axis, dm.n[2]);
+    a.pcshift = pc_shift_real(L, (int)sizeof(C2<T>), npen);
     a.F = F;
     a.fstride = fstride;
     a.G = G;
@@ -434,9 +483,8 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     a.out = out;
     for (int t = 0; t < kMaxTime; ++t) a.w[t] = t < ntime ? w[t] : 0.0;
     const int PC = 1 << a.pcshift;
-    const size_t lds = 2 * (size_t)PC * L * sizeof(C2<T>);
-    const int tiles = real_tiles<T>(dm, axis, 2 * PC);
-    deriv_axis_kernel<T><<<tiles, kFftThreads, lds, st>>>(a);
+    const long long tiles = (npen + 2 * PC - 1) / (2 * PC);
+    deriv_axis_kernel<T><<<(unsigned)tiles, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(a);
     return hipGetLastError();
 }
 
@@ -452,20 +500,21 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
     }
     {
         const int L = dm.n[2];
-        const int sh = pc_shift_for(L, (int)sizeof(C2<TC>), dm.n[0] * dm.n[1]);
+        const long long rows = (long long)dm.n[0] * dm.n[1];
+        const int sh = pc_shift_real(L, (int)sizeof(C2<TC>), rows);
         const int PC = 1 << sh;
-        const size_t lds = 2 * (size_t)PC * L * sizeof(C2<TC>);
-        dim3 g(real_tiles<TC>(dm, 2, 2 * PC), count);
-        r2c_rows_kernel<TI, TC><<<g, kFftThreads, lds, st>>>(dm, pl.p[2], sh, ip, sp);
+        dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
+        r2c_rows_kernel<TI, TC><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(
+            dm, pl.p[2], sh, ip, sp);
     }
     for (int axis = 1; axis >= 3 - dm.dim; --axis) {
         const int L = dm.n[axis];
-        const int sh = pc_shift_c2c(L, (int)sizeof(C2<TC>), dm.n2h);
+        const long long npen = pencil_count(dm, axis, dm.n2h);
+        const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen);
         const int PC = 1 << sh;
-        const size_t lds = 2 * (size_t)PC * L * sizeof(C2<TC>);
-        const int nch = (dm.n2h + PC - 1) / PC;
-        dim3 g((axis == 1 ? dm.n[0] : dm.n[1]) * nch, count);
-        c2c_axis_kernel<TC><<<g, kFftThreads, lds, st>>>(dm, pl.p[axis], axis, sh, -1, sp);
+        dim3 g((unsigned)((npen + PC - 1) / PC), count);
+        c2c_axis_kernel<TC><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(
+            dm, pl.p[axis], axis, sh, -1, sp);
     }
     return hipGetLastError();
 }
@@ -484,20 +533,21 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
     }
     for (int axis = 3 - dm.dim; axis <= 1; ++axis) {
         const int L = dm.n[axis];
-        const int sh = pc_shift_c2c(L, (int)sizeof(C2<T>), dm.n2h);
+        const long long npen = pencil_count(dm, axis, dm.n2h);
+        const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
         const int PC = 1 << sh;
-        const size_t lds = 2 * (size_t)PC * L * sizeof(C2<T>);
-        const int nch = (dm.n2h + PC - 1) / PC;
-        dim3 g((axis == 1 ? dm.n[0] : dm.n[1]) * nch, count);
-        c2c_axis_kernel<T><<<g, kFftThreads, lds, st>>>(dm, pl.p[axis], axis, sh, +1, sp);
+        dim3 g((unsigned)((npen + PC - 1) / PC), count);
+        c2c_axis_kernel<T><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
+            dm, pl.p[axis], axis, sh, +1, sp);
     }
     {
         const int L = dm.n[2];
-        const int sh = pc_shift_for(L, (int)sizeof(C2<T>), dm.n[0] * dm.n[1]);
+        const long long rows = (long long)dm.n[0] * dm.n[1];
+        const int sh = pc_shift_real(L, (int)sizeof(C2<T>), rows);
         const int PC = 1 << sh;
-        const size_t lds = 2 * (size_t)PC * L * sizeof(C2<T>);
-        dim3 g(real_tiles<T>(dm, 2, 2 * PC), count);
-        c2r_rows_kernel<T><<<g, kFftThreads, lds, st>>>(dm, pl.p[2], sh, T(scale), sp, op);
+        dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
+        c2r_rows_kernel<T><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
+            dm, pl.p[2], sh, T(scale), sp, op);
     }
     return hipGetLastError();
 }

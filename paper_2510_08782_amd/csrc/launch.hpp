@@ -64,12 +64,12 @@ struct SpectralPlans {
 };
 
 // Body-force / divergence derivative along internal axis `axis`:
-//   out = [out +] sum_t w[t] * G_t * d/dx_axis F_t     (G_t = 1 when G == nullptr)
-// F_t = F + t*fstride, G_t = G + t*gstride, t = 0..ntime-1.
+//   out = [out +] sum_t w[t] * G[t] * d/dx_axis F[t]   (G[t] = 1 when G == nullptr)
+// for t = 0..ntime-1 (ntime <= 65); F, G are host arrays of device fields.
 template <typename T>
-hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axis, const T* F,
-                             long long fstride, const T* G, long long gstride, const double* w,
-                             int ntime, int accumulate, T* out, hipStream_t st);
+hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axis,
+                             const T* const* F, const T* const* G, const double* w, int ntime,
+                             int accumulate, T* out, hipStream_t st);
 // Forward real-to-half-spectrum transform of `count` fields (count <= 3):
 // in[c] (real TI, N) -> out[c] (complex TC, NH), computed in precision TC.
 template <typename TI, typename TC>

@@ -216,7 +216,20 @@ class Problem : public ProblemBase {
     SpectralPlans<double> plans64{};  // the FP64 spectrum of v (regulariser)
     std::vector<std::unique_ptr<DevBuf>> bufs;
     DevBuf twbuf[3], twbuf64[3];
-    T *m0, *m1, *mhist, *lam, *dX, *dY, *delta, *cfac, *bfac, *b, *tmp;
+    T *m0, *m1, *dX, *dY, *delta, *cfac, *bfac, *b, *tmp;
+    // State / adjoint storage.  Full mode (checkpoint_every == 1): every m^j
+    // and lam^j.  Checkpoint mode: m^j at the checkpoint times 0, c, 2c, ...,
+    // nt only, c-1 fields for the interior states of a segment (the forward
+    // solve passes through them, the backward sweep recomputes into them),
+    // and c+1 adjoint fields reused segment by segment.
+    bool full = true;
+    int cke = 1;
+    std::vector<int> bnd;             // checkpoint times
+    T* mhist = nullptr;               // full mode: (nt+1) N
+    T* lamh = nullptr;                // full mode: (nt+1) N
+    std::vector<T*> ck, mint, lpool;  // checkpoint mode
+    T* lam_nt = nullptr;
+    T* lam0 = nullptr;
     C2<double>* vh[3];
     CT* wh[3];
     double *partial, *dres;
@@ -305,8 +318,21 @@ class Problem : public ProblemBase {
         const int nt = c.nt;
         m0 = alloc_T(N);
         m1 = alloc_T(N);
-        mhist = alloc_T((nt + 1) * N);
-        lam = alloc_T((nt + 1) * N);
+        cke = c.checkpoint_every;
+        full = cke == 1;
+        for (int j = 0; j < nt; j += cke) bnd.push_back(j);
+        bnd.push_back(nt);
+        if (full) {
+            mhist = alloc_T((nt + 1) * N);
+            lamh = alloc_T((nt + 1) * N);
+            lam_nt = lamh + (long long)nt * N;
+            lam0 = lamh;
+        } else {
+            for (size_t i = 0; i < bnd.size(); ++i) ck.push_back(alloc_T(N));
+            for (int i = 0; i < std::min(cke, nt) - 1; ++i) mint.push_back(alloc_T(N));
+            for (int i = 0; i < std::min(cke, nt) + 1; ++i) lpool.push_back(alloc_T(N));
+            lam_nt = lpool[0];
+        }
         dX = alloc_T(d * N);
         dY = alloc_T(d * N);
         const bool compressible = !c.incompressible;
@@ -339,7 +365,7 @@ class Problem : public ProblemBase {
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 128, hipHostMallocDefault));
         HIPCHK(hipMemcpyAsync(m0, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(m1, m1_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(mhist, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(mstate(0), m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }
 
@@ -426,11 +452,13 @@ class Problem : public ProblemBase {
         });
         if (delta) {
             const double one = 1.0;
-            for (int cc = 0; cc < d; ++cc)
+            for (int cc = 0; cc < d; ++cc) {
+                const T* f = comp(v, cc);
                 run(KC_DERIV, [&] {
-                    return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), comp(v, cc), 0,
-                                                nullptr, 0, &one, 1, cc > 0, delta, st);
+                    return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), &f, nullptr, &one, 1,
+                                                cc > 0, delta, st);
                 });
+            }
         }
         run(KC_CHAR, [&] {
             HIPCHK(launch_zero_bounds<T>(bounds, 3, st));
@@ -464,19 +492,32 @@ class Problem : public ProblemBase {
         y_valid = true;
     }
 
+    // where the forward solve keeps m^j
+    int ck_index(int j) const {
+        for (size_t i = 0; i < bnd.size(); ++i)
+            if (bnd[i] == j) return (int)i;
+        return -1;
+    }
+    T* mstate(int j) {
+        if (full) return mhist + (long long)j * N;
+        const int i = ck_index(j);
+        // interior states: consecutive ones land in different buffers when c > 2,
+        // and with c = 2 no two interior states are consecutive
+        return i >= 0 ? ck[i] : mint[j % (int)mint.size()];
+    }
+
     void forward() {
         for (int j = 0; j < cfg.nt; ++j)
             run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, mhist + j * N, dX, cfac, bounds + 0,
-                                         mhist + (j + 1) * N, st);
+                return launch_sl_step<T>(dm, mstate(j), dX, cfac, bounds + 0, mstate(j + 1), st);
             });
     }
 
     // mismatch sum -> dres[0]; optionally lam^nt = m1 - m^nt
     void mismatch(bool write_lam) {
         run(KC_REDUCE, [&] {
-            return launch_sumsq_diff<T>(mhist + cfg.nt * N, m1, write_lam ? lam + cfg.nt * N : nullptr,
-                                        N, partial, dres, st);
+            return launch_sumsq_diff<T>(mstate(cfg.nt), m1, write_lam ? lam_nt : nullptr, N,
+                                        partial, dres, st);
         });
     }
 
@@ -499,6 +540,86 @@ class Problem : public ProblemBase {
         return finish_J(mis);
     }
 
+    double trap_weight(int t) const {
+        const double w = (t == 0 || t == cfg.nt) ? 0.5 * ht : ht;
+        return cfg.model == GANMRES_CONTINUITY ? -w : w;
+    }
+
+    // body force over the given time levels: advection b += w lam grad m,
+    // continuity b -= w pi grad lam (one launch per axis)
+    void body_force(const std::vector<const T*>& m, const std::vector<const T*>& lam,
+                    const std::vector<double>& w, bool accumulate) {
+        const bool cont = cfg.model == GANMRES_CONTINUITY;
+        for (int cc = 0; cc < d; ++cc)
+            run(KC_DERIV, [&] {
+                return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), cont ? lam.data() : m.data(),
+                                            cont ? m.data() : lam.data(), w.data(), (int)w.size(),
+                                            accumulate ? 1 : 0, comp(b, cc), st);
+            });
+    }
+
+    // adjoint backward in time and the body force b (lam^nt already written)
+    void backward() {
+        const int nt = cfg.nt;
+        if (full) {
+            for (int j = nt - 1; j >= 0; --j)
+                run(KC_SL, [&] {
+                    return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, bounds + 1,
+                                             lamh + (long long)j * N, st);
+                });
+            std::vector<const T*> mp(nt + 1), lp(nt + 1);
+            std::vector<double> w(nt + 1);
+            for (int t = 0; t <= nt; ++t) {
+                mp[t] = mhist + (long long)t * N;
+                lp[t] = lamh + (long long)t * N;
+                w[t] = trap_weight(t);
+            }
+            body_force(mp, lp, w, false);
+            adj_valid = true;
+            return;
+        }
+        // checkpoint mode: segments [bnd[s], bnd[s+1]] from the last to the first
+        const int nseg = (int)bnd.size() - 1;
+        int top = 0;  // lpool index holding lam at the segment's end time
+        for (int sgi = nseg - 1; sgi >= 0; --sgi) {
+            const int j0 = bnd[sgi], j1 = bnd[sgi + 1], len = j1 - j0;
+            std::vector<T*> mp(len + 1), lp(len + 1);
+            mp[0] = ck[sgi];
+            mp[len] = ck[sgi + 1];
+            for (int i = 1; i < len; ++i) {
+                mp[i] = mint[i - 1];
+                T* src = mp[i - 1];
+                T* dst = mp[i];
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, bounds + 0, dst, st); });
+            }
+            std::vector<int> idx;
+            for (int i = 0; i < (int)lpool.size(); ++i)
+                if (i != top) idx.push_back(i);
+            lp[len] = lpool[top];
+            int newtop = top;
+            for (int i = len - 1, q = 0; i >= 0; --i, ++q) {
+                lp[i] = lpool[idx[q]];
+                if (i == 0) newtop = idx[q];
+                T* src = lp[i + 1];
+                T* dst = lp[i];
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, bounds + 1, dst, st); });
+            }
+            // time level j0 belongs to the previous segment, except t = 0
+            const int i0 = sgi == 0 ? 0 : 1;
+            std::vector<const T*> fm, fl;
+            std::vector<double> w;
+            for (int i = i0; i <= len; ++i) {
+                fm.push_back(mp[i]);
+                fl.push_back(lp[i]);
+                w.push_back(trap_weight(j0 + i));
+            }
+            body_force(fm, fl, w, sgi != nseg - 1);
+            top = newtop;
+            if (sgi == 0) lam0 = lp[0];
+        }
+        adj_valid = true;
+    }
+
     double gradient(const void* v, void* g, bool reuse) override {
         double J;
         if (reuse) {
@@ -513,24 +634,7 @@ class Problem : public ProblemBase {
             mismatch(true);
             J = finish_J(nullptr);
         }
-        // adjoint, backward in time
-        for (int j = cfg.nt - 1; j >= 0; --j)
-            run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, lam + (j + 1) * N, dY, bfac, bounds + 1, lam + j * N, st);
-            });
-        adj_valid = true;
-        // body force
-        std::vector<double> w(cfg.nt + 1, ht);
-        w[0] = w[cfg.nt] = 0.5 * ht;
-        const bool cont = cfg.model == GANMRES_CONTINUITY;
-        if (cont)
-            for (auto& x : w) x = -x;
-        for (int cc = 0; cc < d; ++cc)
-            run(KC_DERIV, [&] {
-                return launch_deriv_axis<T>(dm, plans, comp_axis(d, cc), cont ? lam : mhist, N,
-                                            cont ? mhist : lam, N, w.data(), cfg.nt + 1, 0,
-                                            comp(b, cc), st);
-            });
+        backward();
         // assembly g = alpha L v + [P] b
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
@@ -566,7 +670,14 @@ class Problem : public ProblemBase {
         if (j < 0 || j > cfg.nt || (which != 0 && which != 1))
             throw Error(GANMRES_EINVAL, "field index out of range");
         if (which == 1 && !adj_valid) throw Error(GANMRES_ESTATE, "no adjoint solve available");
-        const T* src = (which == 0 ? mhist : lam) + j * N;
+        const T* src = nullptr;
+        if (which == 0) {
+            src = full ? mhist + (long long)j * N : (ck_index(j) >= 0 ? ck[ck_index(j)] : nullptr);
+            if (!src) throw Error(GANMRES_ESTATE, "state not kept (not a checkpoint time)");
+        } else {
+            src = full ? lamh + (long long)j * N : (j == 0 ? lam0 : nullptr);
+            if (!src) throw Error(GANMRES_ESTATE, "adjoint not kept at this time (checkpoint mode)");
+        }
         HIPCHK(hipMemcpyAsync(out, src, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
     }

@@ -92,13 +92,12 @@ struct DerivArgs {
     Dims dm;
     FftPlan<T> pl;
     int axis, pcshift;
-    const T* F;
-    long long fstride;
-    const T* G;
-    long long gstride;
     int ntime;
     int accumulate;
+    int has_g;
     T* out;
+    const T* F[kMaxTime];
+    const T* G[kMaxTime];
     double w[kMaxTime];
 };
 
@@ -139,7 +138,7 @@ __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a)
             if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
         }
         acc[e] = (ok[e] && a.accumulate) ? a.out[off[e]] : T(0);
-        fv[e] = ok[e] ? a.F[off[e]] : T(0);
+        fv[e] = ok[e] ? a.F[0][off[e]] : T(0);
         gv[e] = T(1);
     }
     T* flat = reinterpret_cast<T*>(bufA);
@@ -148,9 +147,9 @@ __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a)
         for (int e = 0; e < kItems; ++e)
             if (slot[e] >= 0) flat[slot[e]] = fv[e];
         __syncthreads();
-        const T* G = a.G ? a.G + t * a.gstride : nullptr;
-        const T* Fn = a.F + (t + 1) * a.fstride;
+        const T* G = a.has_g ? a.G[t] : nullptr;
         const bool more = t + 1 < a.ntime;
+        const T* Fn = more ? a.F[t + 1] : nullptr;
 #pragma unroll
         for (int e = 0; e < kItems; ++e) {
             if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
@@ -463,9 +462,9 @@ inline int pointwise_blocks(long long n) {
 }  // namespace
 
 template <typename T>
-hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axis, const T* F,
-                             long long fstride, const T* G, long long gstride, const double* w,
-                             int ntime, int accumulate, T* out, hipStream_t st) {
+hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axis,
+                             const T* const* F, const T* const* G, const double* w, int ntime,
+                             int accumulate, T* out, hipStream_t st) {
     if (ntime < 1 || ntime > kMaxTime) return hipErrorInvalidValue;
     DerivArgs<T> a;
     a.dm = dm;
@@ -474,14 +473,15 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     const int L = dm.n[axis];
     const long long npen = pencil_count(dm, axis, dm.n[2]);
     a.pcshift = pc_shift_real(L, (int)sizeof(C2<T>), npen);
-    a.F = F;
-    a.fstride = fstride;
-    a.G = G;
-    a.gstride = gstride;
     a.ntime = ntime;
     a.accumulate = accumulate;
+    a.has_g = G != nullptr;
     a.out = out;
-    for (int t = 0; t < kMaxTime; ++t) a.w[t] = t < ntime ? w[t] : 0.0;
+    for (int t = 0; t < kMaxTime; ++t) {
+        a.F[t] = t < ntime ? F[t] : nullptr;
+        a.G[t] = (G && t < ntime) ? G[t] : nullptr;
+        a.w[t] = t < ntime ? w[t] : 0.0;
+    }
     const int PC = 1 << a.pcshift;
     const long long tiles = (npen + 2 * PC - 1) / (2 * PC);
     deriv_axis_kernel<T><<<(unsigned)tiles, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(a);
@@ -590,9 +590,9 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
 }
 
 #define GAN_INST(T)                                                                               \
-    template hipError_t launch_deriv_axis<T>(const Dims&, const SpectralPlans<T>&, int, const T*, \
-                                             long long, const T*, long long, const double*, int,  \
-                                             int, T*, hipStream_t);                               \
+    template hipError_t launch_deriv_axis<T>(const Dims&, const SpectralPlans<T>&, int,           \
+                                             const T* const*, const T* const*, const double*,     \
+                                             int, int, T*, hipStream_t);                          \
     template hipError_t launch_rfft<T, T>(const Dims&, const SpectralPlans<T>&, const T* const*,  \
                                           C2<T>* const*, int, hipStream_t);                       \
     template hipError_t launch_irfft<T>(const Dims&, const SpectralPlans<T>&, C2<T>* const*,      \

@@ -1,0 +1,98 @@
+"""GPU tests at the study's full sizes and of the support features:
+checkpointed state history, the autograd Function, finite differences.
+
+  * c1 (2-D continuity 256^2, H2, nt=8, FP32): gradient through the
+    torch.autograd.Function backward against the oracle gradient and against
+    central differences (h = 1e-3, 10 smooth random directions) of the FP64
+    objective; the FD-vs-gradient gap may exceed the oracle's own
+    optimize-then-discretize gap on the same direction by at most 1e-4.
+  * checkpointed history (every c-th state kept, the rest recomputed in the
+    backward sweep) against the oracle and against the full history.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests._cases import as_precision, oracle_problem, probes, rel, round_to, smooth_direction
+from tests.test_gpu_parity import TOL, check_probe, dev, host, make_gpu
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("c,nt", [(2, 4), (3, 5), (4, 3)])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_checkpointed_history(c, nt, prec):
+    import paper_2510_08782_amd as gan
+    say(f"checkpoint every {c}, nt {nt}, {prec}")
+    wl = synth.workload("c3", shape=(24, 32, 36))
+    P = as_precision(oracle_problem(wl, nt=nt), prec)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    G = gan.Problem(dev(P.m0, dtype), dev(P.m1, dtype), nt, P.alpha, P.p,
+                    checkpoint_every=c)
+    F = make_gpu(P, wl, dtype)
+    for pname, v in probes(wl).items():
+        v = round_to(v, prec)
+        check_probe(P, G, v, dtype, TOL[prec], pname)
+        _, g1 = G.eval_gradient(dev(v, dtype))
+        _, g2 = F.eval_gradient(dev(v, dtype))
+        assert rel(host(g1), host(g2)) <= (1e-13 if prec == "f64" else 1e-6)
+    if c < nt:
+        assert G.workspace_bytes() < F.workspace_bytes()
+    else:
+        assert G.workspace_bytes() <= F.workspace_bytes()
+    with pytest.raises(gan.GanmresError):
+        G.get_field("state", 1)          # not a checkpoint time
+    G.get_field("state", min(c, nt))
+
+
+def test_c1_autograd_and_finite_differences():
+    import paper_2510_08782_amd as gan
+    say("c1 256^2 continuity FP32: autograd backward, oracle gradient, central FD")
+    wl = synth.workload("c1")
+    P64 = oracle_problem(wl)
+    P = as_precision(P64, "f32")
+    v = round_to(0.5 * wl.vstar, "f32")
+    G32 = make_gpu(P, wl, torch.float32)
+    G64 = make_gpu(P, wl, torch.float64)
+    TransportObjective = gan.transport_objective()
+    vt = dev(v, torch.float32).requires_grad_(True)
+    J = TransportObjective.apply(vt, G32)
+    J.backward()
+    Jo, go = P.gradient(v)
+    cell = P.grid.cell
+    assert abs(J.item() - Jo) <= 1e-4 * abs(Jo)
+    err = rel(host(vt.grad), cell * go)
+    say(f"  autograd grad vs oracle: rel err {err:.2e}")
+    assert err <= 1e-4
+    hfd = 1e-3
+    vmax = np.abs(wl.vstar).max()
+    for k in range(10):
+        d = smooth_direction(wl.shape, 100 + k)
+        d = d * (vmax / np.abs(d).max())
+        fd = (G64.eval_objective(dev(v + hfd * d, torch.float64)) -
+              G64.eval_objective(dev(v - hfd * d, torch.float64))) / (2 * hfd)
+        an = float(np.sum(host(vt.grad) * d))
+        fd_o = (P.objective(v + hfd * d) - P.objective(v - hfd * d)) / (2 * hfd)
+        an_o = cell * float(np.sum(go * d))
+        gap, gap_o = abs(fd - an) / abs(an), abs(fd_o - an_o) / abs(an_o)
+        say(f"  dir {k}: FD {fd:.8e} grad {an:.8e} gap {gap:.2e} (oracle gap {gap_o:.2e})")
+        assert abs(fd - fd_o) <= 1e-8 * abs(fd_o) + 1e-12
+        assert gap <= gap_o + 1e-4
+
+
+def test_c1_full_size_probe_parity():
+    say("c1 256^2 FP32 probes")
+    wl = synth.workload("c1")
+    P = as_precision(oracle_problem(wl), "f32")
+    G = make_gpu(P, wl, torch.float32)
+    for pname, v in probes(wl).items():
+        check_probe(P, G, round_to(v, "f32"), torch.float32, TOL["f32"], pname)

@@ -54,7 +54,12 @@ def check_probe(P, G, v, dtype, tol, name):
     lam_scale = max(np.abs(st["lam"][-1]).max(), 1e-300)
     lam0 = host(G.get_field("adjoint", 0))
     if np.abs(st["lam"][0]).max() > 0:
-        assert rel(lam0, st["lam"][0]) <= tol, name
+        # lam^nt = m1 - m(1) cancels: the relative rounding error of m(1)
+        # (<= 2e-6 in FP32 after the transport, 1e-14 in FP64) is amplified
+        # by kappa = |m(1)| / |lam^nt|, which grows near the optimum
+        kappa = np.linalg.norm(st["m"][-1]) / max(np.linalg.norm(st["lam"][-1]), 1e-300)
+        tol_lam = tol + (2e-6 if tol > 1e-8 else 1e-14) * kappa
+        assert rel(lam0, st["lam"][0]) <= tol_lam, (name, kappa)
     else:
         assert np.abs(lam0).max() <= tol * lam_scale
     err = rel(host(g), go)

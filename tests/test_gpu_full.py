@@ -96,3 +96,66 @@ def test_c1_full_size_probe_parity():
     G = make_gpu(P, wl, torch.float32)
     for pname, v in probes(wl).items():
         check_probe(P, G, round_to(v, "f32"), torch.float32, TOL["f32"], pname)
+
+
+def test_c2_full_size_gradient_parity():
+    """c2 (3-D 128^3 incompressible, H1, nt=4), FP32 and FP64, at v*/2 against
+    the oracle gradient (the launch configuration the benchmark times)."""
+    say("c2 128^3: oracle gradient (about a minute on the host)")
+    wl = synth.workload("c2")
+    P64 = oracle_problem(wl)
+    for prec in ("f64", "f32"):
+        P = as_precision(P64, prec)
+        v = round_to(0.5 * wl.vstar, prec)
+        Jo, go = P.gradient(v)
+        dtype = torch.float64 if prec == "f64" else torch.float32
+        G = make_gpu(P, wl, dtype)
+        J, g = G.eval_gradient(dev(v, dtype))
+        err = rel(host(g), go)
+        say(f"  {prec}: J {J:.12e} / {Jo:.12e}, grad rel err {err:.2e}")
+        assert abs(J - Jo) <= TOL[prec] * abs(Jo)
+        assert err <= TOL[prec]
+        # the gradient of the incompressible model is divergence-free
+        from oracle import spectral as sp
+        div = sp.divergence(P.grid, host(g))
+        assert np.abs(div).max() <= (1e-10 if prec == "f64" else 1e-4) * np.abs(host(g)).max()
+        G.close()
+
+
+def test_c3_full_size_properties():
+    """c3 (3-D 256^3 advection, H2, nt=8, checkpoint every 2): the oracle is too
+    slow here, so check properties that hold at any size: the FP32
+    checkpointed gradient against the FP64 full-history gradient, a central
+    difference of the FP64 objective along v*, and the state at the
+    checkpoint times against a full-history run."""
+    import paper_2510_08782_amd as gan
+    say("c3 256^3: FP32 checkpointed vs FP64 plain")
+    wl = synth.workload("c3")
+    dev64 = lambda x: dev(x, torch.float64)
+    # both runs see the FP32-representable inputs: with H2 at 256^3 the
+    # regulariser amplifies the rounding of v itself far above 1e-4
+    m0 = dev64(round_to(wl.m0, "f32"))
+    gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order)
+    gen.eval_objective(dev64(wl.vstar))
+    m1 = gen.get_field("state", wl.nt)
+    gen.close()
+    m1 = m1.float().double()
+    v = round_to(0.5 * wl.vstar, "f32")
+    G64 = gan.Problem(m0, m1, wl.nt, wl.alpha, wl.reg_order)
+    J64, g64 = G64.eval_gradient(dev64(v))
+    G32 = gan.Problem(m0.float(), m1.float(), wl.nt, wl.alpha, wl.reg_order, checkpoint_every=2)
+    v32 = dev(v, torch.float32)
+    J32, g32 = G32.eval_gradient(v32)
+    err = rel(host(g32), host(g64))
+    say(f"  J {J32:.10e} / {J64:.10e}  grad FP32 vs FP64 rel {err:.2e}")
+    assert abs(J32 - J64) <= 1e-4 * abs(J64)
+    assert err <= 1e-4
+    hfd = 1e-4
+    d = dev64(wl.vstar)
+    fd = (G64.eval_objective(dev64(v) + hfd * d) - G64.eval_objective(dev64(v) - hfd * d)) / (2 * hfd)
+    cell = (2 * math.pi / 256) ** 3
+    an = cell * float(torch.sum(g64 * d))
+    say(f"  FD along v*: {fd:.8e} vs <g, v*>_h {an:.8e}")
+    assert abs(fd - an) <= 5e-3 * abs(an)
+    G32.close()
+    G64.close()

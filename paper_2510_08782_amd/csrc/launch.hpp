@@ -91,10 +91,19 @@ struct SpecOpParams {
 template <typename T>
 hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
                                 C2<T>* const* bh, C2<T>* const* gh, hipStream_t st);
-// sh[c] = -P gh[c] / (alpha lbar_p)   (in place allowed)
+// sh[c] = -P gh[c] / (alpha lbar_p)   (in place allowed); keep (nullable)
+// receives a second copy
 template <typename T>
 hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
-                               C2<T>* const* sh, hipStream_t st);
+                               C2<T>* const* sh, C2<T>* const* keep, hipStream_t st);
+// res[0] = sum w l_p Re(vh conj sh), res[1] = sum w l_p |sh|^2 (full-spectrum sums)
+template <typename T>
+hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
+                             C2<T>* const* sh, double* partial, double* res, hipStream_t st);
+// vh[c] += rho sh[c]
+template <typename T>
+hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, double rho,
+                            C2<T>* const* sh, hipStream_t st);
 // res[0] = sum_c sum_k l_p(k) |vh_c(k)|^2 over the full spectrum (half-spectrum weights)
 template <typename T>
 hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* const* vh,

@@ -232,6 +232,9 @@ class Problem : public ProblemBase {
     T* lam0 = nullptr;
     C2<double>* vh[3];
     CT* wh[3];
+    CT* sk[3];                   // spectrum of the last search direction (line search)
+    const void* vh_of = nullptr;  // velocity whose spectrum vh holds
+    bool reg_from_device = true;  // R(v) of the next finish_J comes from the device sum
     double *partial, *dres;
     int* bounds;  // device: [0] dX, [1] dY, [2] predictor
     double* hres;  // pinned host results
@@ -350,6 +353,7 @@ class Problem : public ProblemBase {
                 vh[cc] = static_cast<C2<double>*>(bufs.back()->p);
             }
             wh[cc] = cc < d ? alloc_C(NH) : nullptr;
+            sk[cc] = cc < d ? alloc_C(NH) : nullptr;
         }
         {
             bufs.emplace_back(new DevBuf);
@@ -444,12 +448,20 @@ class Problem : public ProblemBase {
     // -- per-velocity preparation ---------------------------------------------
     // v^, R(v) (device scalar -> reg_cached), divergence, departure points and
     // stationary source factors.
-    void prepare(const void* v, bool needY) {
+    void spectrum_of(const void* v) {
         const T* vin[3] = {comp(v, 0), comp(v, 1), d == 3 ? comp(v, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vh, d, st); });
         run(KC_REDUCE, [&] {
             return launch_spec_regvalue<double>(dm, specop(false), vh, partial, dres + 64, st);
         });
+        vh_of = v;
+        reg_from_device = true;
+    }
+
+    // trial = true: a line-search trial whose R(v) the caller supplies and
+    // whose spectrum is not needed (vh keeps the current iterate's)
+    void prepare(const void* v, bool needY, bool trial = false) {
+        if (!trial) spectrum_of(v);
         if (delta) {
             const double one = 1.0;
             for (int cc = 0; cc < d; ++cc) {
@@ -525,9 +537,22 @@ class Problem : public ProblemBase {
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 128, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const double mis = 0.5 * cell * hres[0];
-        reg_cached = cell / double(N) * hres[64];
+        if (reg_from_device) reg_cached = cell / double(N) * hres[64];
         if (mis_out) *mis_out = mis;
         return mis + 0.5 * cfg.alpha * reg_cached;
+    }
+
+    // J at a line-search trial v with a known regulariser value R
+    double objective_trial(const void* v, double R) {
+        prepare(v, false, true);
+        forward();
+        mismatch(false);
+        fwd_valid = true;
+        fwd_v = v;
+        adj_valid = false;
+        reg_cached = R;
+        reg_from_device = false;
+        return finish_J(nullptr);
     }
 
     double objective(const void* v, bool keep, double* mis) override {
@@ -646,11 +671,14 @@ class Problem : public ProblemBase {
         return J;
     }
 
-    double precond(const void* g, void* s) override {
+    double precond(const void* g, void* s) override { return precond_keep(g, s, false); }
+
+    double precond_keep(const void* g, void* s, bool keep) {
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
         run(KC_SPEC, [&] {
-            return launch_spec_precond<T>(dm, specop(cfg.incompressible != 0), wh, wh, st);
+            return launch_spec_precond<T>(dm, specop(cfg.incompressible != 0), wh, wh,
+                                          keep ? sk : nullptr, st);
         });
         T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / N, d, st); });
@@ -739,14 +767,29 @@ class Problem : public ProblemBase {
         T* q = static_cast<T*>(qb->p);
         T* gq = static_cast<T*>(gqb->p);
         T* s = static_cast<T*>(sb->p);
-        // direction and line search (eqs. e:rpgd, e:armijo)
-        const double gs = precond(rg(cur), s);
-        double rho = rho_bar, Jq = 0.0;
+        // direction and line search (eqs. e:rpgd, e:armijo).  Along the line the
+        // regulariser is a quadratic in rho: R(v + rho s) = R(v) + 2 rho <v,L s>_h
+        // + rho^2 <s,L s>_h, and the spectrum of the accepted trial is
+        // v^ + rho s^; trials therefore need no transform of their own.
+        if (vh_of != rv(cur)) {
+            spectrum_of(rv(cur));
+            HIPCHK(hipMemcpyAsync(hres, dres + 64, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            reg_cached = cell / double(N) * hres[0];
+        }
+        const double R0 = reg_cached;
+        const double gs = precond_keep(rg(cur), s, true);
+        run(KC_REDUCE, [&] { return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres, st); });
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const double cA = cell / double(N) * hres[0], cB = cell / double(N) * hres[1];
+        double rho = rho_bar, Jq = 0.0, Rq = R0;
         int trials = 0;
         bool accepted = false;
         for (int t = 0; t <= p.max_backtracks; ++t) {
             run(KC_VEC, [&] { return launch_axpy<T>(rv(cur), rho, s, q, d * N, st); });
-            Jq = objective(q, true, nullptr);
+            Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
+            Jq = objective_trial(q, Rq);
             ++trials;
             if (Jq < Jcur + p.c_armijo * rho * gs) {
                 rho_bar = (t == 0) ? 2.0 * rho : rho;
@@ -758,6 +801,10 @@ class Problem : public ProblemBase {
         }
         info.n_trials = trials;
         if (!accepted) throw Error(GANMRES_ELINESEARCH, "Armijo condition not met");
+        run(KC_SPEC, [&] { return launch_spec_axpy<T>(dm, d, vh, rho, sk, st); });
+        vh_of = q;
+        reg_cached = Rq;
+        reg_from_device = false;
         const double Jq_grad = gradient(q, gq, true);
         (void)Jq_grad;
         ++ngrad;

@@ -414,7 +414,8 @@ __global__ void spec_gradient_kernel(Dims dm, SpecOpParams sp, SpecPtrs<double> 
 }
 
 template <typename T>
-__global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, SpecPtrs<T> sh) {
+__global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, SpecPtrs<T> sh,
+                                    SpecPtrs<T> keep, int has_keep) {
     for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
          lin += (long long)gridDim.x * blockDim.x) {
         const KVec kv = kvec(dm, lin);
@@ -427,7 +428,59 @@ __global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, Sp
         if (sp.leray) leray_point(kv, sp.dim, g);
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-            if (c < sp.dim) sh.spec[c][lin] = cscale(g[c], f);
+            if (c < sp.dim) {
+                const C2<T> z = cscale(g[c], f);
+                sh.spec[c][lin] = z;
+                if (has_keep) keep.spec[c][lin] = z;
+            }
+    }
+}
+
+// Cross terms of the regulariser along a line: with the half-spectrum
+// weights (1 at k2 = 0 and at the Nyquist index, else 2),
+//   res[0] = sum w l_p Re(vh conj(sh)),  res[1] = sum w l_p |sh|^2.
+template <typename T>
+__global__ void __launch_bounds__(256) spec_cross_kernel(Dims dm, SpecOpParams sp,
+                                                         SpecPtrs<double> vh, SpecPtrs<T> sh,
+                                                         double* partial) {
+    __shared__ double red[256 / 64];
+    double a = 0.0, b = 0.0;
+    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+         lin += (long long)gridDim.x * blockDim.x) {
+        const KVec kv = kvec(dm, lin);
+        const int i2 = (int)(lin % dm.n2h);
+        const double wl = ((i2 == 0 || 2 * i2 == dm.n[2]) ? 1.0 : 2.0) * ipow(kv.k2, sp.p);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= sp.dim) continue;
+            const C2<double> z = vh.spec[c][lin];
+            const C2<T> q = sh.spec[c][lin];
+            a += wl * (z.x * double(q.x) + z.y * double(q.y));
+            b += wl * (double(q.x) * double(q.x) + double(q.y) * double(q.y));
+        }
+    }
+    const double ra = block_reduce<false>(a, red);
+    const double rb = block_reduce<false>(b, red);
+    if (threadIdx.x == 0) {
+        partial[blockIdx.x] = ra;
+        partial[gridDim.x + blockIdx.x] = rb;
+    }
+}
+
+// vh[c] += rho * sh[c]  (FP64 spectrum of v updated along a line)
+template <typename T>
+__global__ void spec_axpy_kernel(Dims dm, int dim, SpecPtrs<double> vh, double rho, SpecPtrs<T> sh) {
+    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+         lin += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= dim) continue;
+            C2<double> z = vh.spec[c][lin];
+            const C2<T> q = sh.spec[c][lin];
+            z.x += rho * double(q.x);
+            z.y += rho * double(q.y);
+            vh.spec[c][lin] = z;
+        }
     }
 }
 
@@ -568,13 +621,42 @@ hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<doubl
 
 template <typename T>
 hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
-                               C2<T>* const* sh, hipStream_t st) {
-    SpecPtrs<T> a{}, b{};
+                               C2<T>* const* sh, C2<T>* const* keep, hipStream_t st) {
+    SpecPtrs<T> a{}, b{}, k{};
     for (int c = 0; c < sp.dim; ++c) {
         a.spec[c] = gh[c];
         b.spec[c] = sh[c];
+        k.spec[c] = keep ? keep[c] : nullptr;
     }
-    spec_precond_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b);
+    spec_precond_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, k, keep != nullptr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
+                             C2<T>* const* sh, double* partial, double* res, hipStream_t st) {
+    SpecPtrs<double> a{};
+    SpecPtrs<T> b{};
+    for (int c = 0; c < sp.dim; ++c) {
+        a.spec[c] = vh[c];
+        b.spec[c] = sh[c];
+    }
+    const int nb = reduction_blocks(dm.NH);
+    spec_cross_kernel<T><<<nb, 256, 0, st>>>(dm, sp, a, b, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 2, res);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, double rho,
+                            C2<T>* const* sh, hipStream_t st) {
+    SpecPtrs<double> a{};
+    SpecPtrs<T> b{};
+    for (int c = 0; c < dim; ++c) {
+        a.spec[c] = vh[c];
+        b.spec[c] = sh[c];
+    }
+    spec_axpy_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, dim, a, rho, b);
     return hipGetLastError();
 }
 
@@ -601,7 +683,11 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
                                                 C2<double>* const*, C2<T>* const*, C2<T>* const*, \
                                                 hipStream_t);                                     \
     template hipError_t launch_spec_precond<T>(const Dims&, const SpecOpParams&, C2<T>* const*,   \
-                                               C2<T>* const*, hipStream_t);                       \
+                                               C2<T>* const*, C2<T>* const*, hipStream_t);        \
+    template hipError_t launch_spec_cross<T>(const Dims&, const SpecOpParams&, C2<double>* const*, \
+                                             C2<T>* const*, double*, double*, hipStream_t);       \
+    template hipError_t launch_spec_axpy<T>(const Dims&, int, C2<double>* const*, double,         \
+                                            C2<T>* const*, hipStream_t);                          \
     template hipError_t launch_spec_regvalue<T>(const Dims&, const SpecOpParams&, C2<T>* const*,  \
                                                 double*, double*, hipStream_t);
 GAN_INST(float)

@@ -7,29 +7,28 @@
 namespace gan {
 
 // ---- semi-Lagrangian kernels (sl.hip) --------------------------------------
-// Displacement bounds are device ints: ceil(max |d|) of a displacement field.
-// bounds[0]: state departure dX, bounds[1]: adjoint departure dY,
-// bounds[2]: predictor (max |u|).  The gathers read them to pick the LDS path.
+// Displacement bounds are host ints, upper bounds on max |d| in cells; each
+// launcher picks the LDS halo variant that covers its bound.
+// max over components and points of |s_c v_c(i)| -> res[0] (FP64 reduction)
 template <typename T>
-hipError_t launch_zero_bounds(int* bounds, int n, hipStream_t st);
-// bounds_u = ceil(max_c max_i |s_c v_c(i)|)  (accumulated with atomicMax)
-template <typename T>
-hipError_t launch_velocity_bound(const Dims& dm, const T* v, const double* s, int* bound_u,
-                                 hipStream_t st);
+hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, double* partial,
+                               double* res, hipStream_t st);
+// Upper bound (cells) of the RK2 departure displacements given max |u|.
+int displacement_bound(double umax, int dim);
 // RK2 departure displacements (index units) for velocity +v (dX, nullable) and
-// -v (dY, nullable).  s[c] = h_t / h_c converts component c to cells per step.
-// Accumulates the bounds of dX / dY into bound_out[0] / bound_out[1].
+// -v (dY, nullable).  s[c] = h_t / h_c converts component c to cells per step;
+// ubound >= max |u|.
 template <typename T>
-hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, const int* ubound,
-                                  T* dX, T* dY, int* bound_out, hipStream_t st);
-// out = [fac *] I[src](i + disp); `bound` is the bound of disp
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int ubound, T* dX,
+                                  T* dY, hipStream_t st);
+// out = [fac *] I[src](i + disp); bound >= max |disp|
 template <typename T>
-hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac,
-                          const int* bound, T* out, hipStream_t st);
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int bound,
+                          T* out, hipStream_t st);
 // out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, const int* bound, T* out, hipStream_t st);
+                                double sgn, int bound, T* out, hipStream_t st);
 
 // ---- reductions and vector kernels (vec.hip) -------------------------------
 // Deterministic two-stage FP64 reductions; the result lands in res[0] (device).

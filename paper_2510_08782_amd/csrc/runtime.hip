@@ -236,7 +236,10 @@ class Problem : public ProblemBase {
     const void* vh_of = nullptr;  // velocity whose spectrum vh holds
     bool reg_from_device = true;  // R(v) of the next finish_J comes from the device sum
     double *partial, *dres;
-    int* bounds;  // device: [0] dX, [1] dY, [2] predictor
+    // displacement bounds of the velocity whose departure points are current
+    double umax = 0.0;              // >= max |u| (cells per step)
+    int ubound = 0, dbound = 0;     // ceil bounds for the predictor and for X / Y
+    const void* umax_of = nullptr;  // velocity umax belongs to
     double* hres;  // pinned host results
     long long ws_bytes = 0;
     bool fwd_valid = false;
@@ -362,9 +365,7 @@ class Problem : public ProblemBase {
             bufs.emplace_back(new DevBuf);
             bufs.back()->alloc(sizeof(double) * 128);
             dres = static_cast<double*>(bufs.back()->p);
-            bufs.emplace_back(new DevBuf);
-            bufs.back()->alloc(sizeof(int) * 8);
-            bounds = static_cast<int*>(bufs.back()->p);
+
         }
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 128, hipHostMallocDefault));
         HIPCHK(hipMemcpyAsync(m0, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
@@ -458,10 +459,27 @@ class Problem : public ProblemBase {
         reg_from_device = true;
     }
 
+    void set_bounds(const void* v, double um) {
+        umax = um;
+        umax_of = v;
+        ubound = !(um <= 1.0e6) ? (1 << 20) : static_cast<int>(std::ceil(um * (1.0 + 1e-6)));
+        dbound = displacement_bound(um, d);
+    }
+
+    // max |u| of a velocity (reduction + sync)
+    double velocity_max(const void* v) {
+        run(KC_REDUCE, [&] {
+            return launch_velocity_max<T>(dm, static_cast<const T*>(v), cscale, partial, dres, st);
+        });
+        return fetch();
+    }
+
     // trial = true: a line-search trial whose R(v) the caller supplies and
-    // whose spectrum is not needed (vh keeps the current iterate's)
-    void prepare(const void* v, bool needY, bool trial = false) {
+    // whose spectrum is not needed (vh keeps the current iterate's); umax_known
+    // >= 0 is a known bound on max |u| of v (else it is reduced on the device)
+    void prepare(const void* v, bool needY, bool trial = false, double umax_known = -1.0) {
         if (!trial) spectrum_of(v);
+        set_bounds(v, umax_known >= 0.0 ? umax_known : velocity_max(v));
         if (delta) {
             const double one = 1.0;
             for (int cc = 0; cc < d; ++cc) {
@@ -473,33 +491,30 @@ class Problem : public ProblemBase {
             }
         }
         run(KC_CHAR, [&] {
-            HIPCHK(launch_zero_bounds<T>(bounds, 3, st));
-            HIPCHK(launch_velocity_bound<T>(dm, static_cast<const T*>(v), cscale, bounds + 2, st));
-            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, bounds + 2, dX,
-                                             needY ? dY : nullptr, bounds, st);
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, ubound, dX,
+                                             needY ? dY : nullptr, st);
         });
         y_valid = needY;
         if (cfac)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dX, ht, -1.0, bounds + 0, cfac, st);
+                return launch_source_factor<T>(dm, delta, dX, ht, -1.0, dbound, cfac, st);
             });
         if (bfac && needY)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bounds + 1, bfac, st);
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st);
             });
     }
 
     void ensure_Y(const void* v) {
         if (y_valid) return;
-        // characteristics for -v only; the predictor bound of v is still current
+        // characteristics for -v only; the bounds of v are still current
         run(KC_CHAR, [&] {
-            HIPCHK(launch_zero_bounds<T>(bounds + 1, 1, st));
-            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, bounds + 2,
-                                             nullptr, dY, bounds, st);
+            return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, ubound, nullptr,
+                                             dY, st);
         });
         if (bfac)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, bounds + 1, bfac, st);
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st);
             });
         y_valid = true;
     }
@@ -521,7 +536,7 @@ class Problem : public ProblemBase {
     void forward() {
         for (int j = 0; j < cfg.nt; ++j)
             run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, mstate(j), dX, cfac, bounds + 0, mstate(j + 1), st);
+                return launch_sl_step<T>(dm, mstate(j), dX, cfac, dbound, mstate(j + 1), st);
             });
     }
 
@@ -543,8 +558,8 @@ class Problem : public ProblemBase {
     }
 
     // J at a line-search trial v with a known regulariser value R
-    double objective_trial(const void* v, double R) {
-        prepare(v, false, true);
+    double objective_trial(const void* v, double R, double um) {
+        prepare(v, false, true, um);
         forward();
         mismatch(false);
         fwd_valid = true;
@@ -589,7 +604,7 @@ class Problem : public ProblemBase {
         if (full) {
             for (int j = nt - 1; j >= 0; --j)
                 run(KC_SL, [&] {
-                    return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, bounds + 1,
+                    return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
                                              lamh + (long long)j * N, st);
                 });
             std::vector<const T*> mp(nt + 1), lp(nt + 1);
@@ -615,7 +630,7 @@ class Problem : public ProblemBase {
                 mp[i] = mint[i - 1];
                 T* src = mp[i - 1];
                 T* dst = mp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, bounds + 0, dst, st); });
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, dbound, dst, st); });
             }
             std::vector<int> idx;
             for (int i = 0; i < (int)lpool.size(); ++i)
@@ -627,7 +642,7 @@ class Problem : public ProblemBase {
                 if (i == 0) newtop = idx[q];
                 T* src = lp[i + 1];
                 T* dst = lp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, bounds + 1, dst, st); });
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, dbound, dst, st); });
             }
             // time level j0 belongs to the previous segment, except t = 0
             const int i0 = sgi == 0 ? 0 : 1;
@@ -686,8 +701,17 @@ class Problem : public ProblemBase {
             return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), d * N, partial,
                                  dres, st);
         });
-        return cell * fetch();
+        if (keep)
+            run(KC_REDUCE, [&] {
+                return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial, dres + 2,
+                                              st);
+            });
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        smax = hres[2];
+        return cell * hres[0];
     }
+    double smax = 0.0;  // max |u| of the last kept search direction
 
     double maxabs(const T* a) {
         run(KC_REDUCE, [&] { return launch_maxabs<T>(a, d * N, partial, dres, st); });
@@ -777,7 +801,8 @@ class Problem : public ProblemBase {
             HIPCHK(hipStreamSynchronize(st));
             reg_cached = cell / double(N) * hres[0];
         }
-        const double R0 = reg_cached;
+        if (umax_of != rv(cur)) set_bounds(rv(cur), velocity_max(rv(cur)));
+        const double R0 = reg_cached, um0 = umax;
         const double gs = precond_keep(rg(cur), s, true);
         run(KC_REDUCE, [&] { return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres, st); });
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
@@ -789,7 +814,7 @@ class Problem : public ProblemBase {
         for (int t = 0; t <= p.max_backtracks; ++t) {
             run(KC_VEC, [&] { return launch_axpy<T>(rv(cur), rho, s, q, d * N, st); });
             Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
-            Jq = objective_trial(q, Rq);
+            Jq = objective_trial(q, Rq, um0 + rho * smax);
             ++trials;
             if (Jq < Jcur + p.c_armijo * rho * gs) {
                 rho_bar = (t == 0) ? 2.0 * rho : rho;

@@ -9,15 +9,15 @@
 // FP32 whatever the grid index.
 //
 // LDS-tiled gather.  A block owns a tile of output points (3-D: 32 x 8 x TZ,
-// 2-D: 64 x 32) and stages the source field over the tile plus a fixed halo
-// of HALO+1 cells below and HALO+2 above every axis, loaded row by row with
-// coalesced reads.  Every tap then comes from LDS at a compile-time offset
-// from one base address per point.  The halo covers departure displacements
-// up to HALO cells; the bound of the current displacement field is computed
-// on the device (ceil of max |d|, one int per field) and read by the kernel,
-// which switches the whole launch to a direct global gather when the bound
-// exceeds HALO (large line-search trial steps).  The fallback gives the same
-// values: only where the taps are read from changes.
+// 2-D: 64 x 32) and stages the source field over the tile plus a halo of
+// H+1 cells below and H+2 above every axis.  Every tap then comes from LDS at
+// a compile-time offset from one base address per point.  The caller passes
+// an upper bound on the displacement (cells); the launcher picks the smallest
+// halo variant that covers it, and a launch whose bound exceeds its halo takes
+// the direct global gather instead.  Both paths give the same values: only
+// where the taps are read from changes.
+#include <cmath>
+
 #include "launch.hpp"
 #include "reduce.hpp"
 
@@ -96,37 +96,32 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
 
 // ---- tile geometry -----------------------------------------------------------
 // 3-D: threads (32 x 8), each owns TZ points along z.  2-D: threads (64 x 4),
-// each owns 8 points along y (tile 64 x 32).
-template <typename T, int DIM>
+// each owns 8 points along y (tile 64 x 32).  H is the halo: the staged region
+// covers departure displacements of up to H cells.
+template <typename T_, int DIM_, int H>
 struct Tile;
-#ifndef GAN_SL_TZ32
-#define GAN_SL_TZ32 8
-#endif
-#ifndef GAN_SL_HALO3
-#define GAN_SL_HALO3 2
-#endif
-#ifndef GAN_SL_TX3
-#define GAN_SL_TX3 32
-#endif
-template <typename T>
-struct Tile<T, 3> {
-    static constexpr int TX = GAN_SL_TX3, TY = 256 / GAN_SL_TX3, TZ = sizeof(T) == 4 ? GAN_SL_TZ32 : 4;
-    static constexpr int HALO = GAN_SL_HALO3;
-    static constexpr int RX = TX + 2 * HALO + 3, RY = TY + 2 * HALO + 3, RZ = TZ + 2 * HALO + 3;
+template <typename T_, int H>
+struct Tile<T_, 3, H> {
+    using T = T_;
+    static constexpr int DIM = 3;
+    static constexpr int TX = 32, TY = 8, TZ = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int HALO = H;
+    static constexpr int RX = TX + 2 * H + 3, RY = TY + 2 * H + 3, RZ = TZ + 2 * H + 3;
     static constexpr int PTS = TZ;  // points per thread
 };
-template <typename T>
-struct Tile<T, 2> {
+template <typename T_, int H>
+struct Tile<T_, 2, H> {
+    using T = T_;
+    static constexpr int DIM = 2;
     static constexpr int TX = 64, TY = 32, TZ = 1;
-    static constexpr int HALO = 4;
-    static constexpr int RX = TX + 2 * HALO + 3, RY = TY + 2 * HALO + 3, RZ = 1;
+    static constexpr int HALO = H;
+    static constexpr int RX = TX + 2 * H + 3, RY = TY + 2 * H + 3, RZ = 1;
     static constexpr int PTS = 8;
 };
 
-template <typename T, int DIM>
+template <class C>
 constexpr size_t tile_lds_bytes() {
-    using C = Tile<T, DIM>;
-    return sizeof(T) * C::RX * C::RY * C::RZ;
+    return sizeof(typename C::T) * C::RX * C::RY * C::RZ;
 }
 
 // g mod n in [0, n): the common in-range case costs one compare.
@@ -140,10 +135,10 @@ __device__ inline int wrapn(int g, int n) {
 // writing dword l of the row; the wrapped x index of every lane is computed
 // once.  All of a wave's row loads are in flight together and no VGPRs hold
 // the data.  FP64 rows move as pairs of dwords.  Ends with a barrier.
-template <typename T, int DIM>
-__device__ inline void stage(const Dims& dm, const T* __restrict__ src, T* lds, int x0, int y0,
-                             int z0) {
-    using C = Tile<T, DIM>;
+template <class C>
+__device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ src,
+                             typename C::T* lds, int x0, int y0, int z0) {
+    using T = typename C::T;
     constexpr int W = sizeof(T) / 4;                  // dwords per element
     constexpr int ROWS = C::RY * C::RZ;
     constexpr int NW = kThreads / 64;
@@ -161,7 +156,7 @@ __device__ inline void stage(const Dims& dm, const T* __restrict__ src, T* lds, 
     for (int r = wave; r < ROWS; r += NW) {
         const int ry = r % C::RY, rz = r / C::RY;
         const int gy = wrapn(y0 - C::HALO - 1 + ry, dm.n[1]);
-        const int gz = DIM == 3 ? wrapn(z0 - C::HALO - 1 + rz, dm.n[0]) : 0;
+        const int gz = C::DIM == 3 ? wrapn(z0 - C::HALO - 1 + rz, dm.n[0]) : 0;
         // N < 2^31 elements
         const unsigned* row = reinterpret_cast<const unsigned*>(src + (gz * dm.n[1] + gy) * dm.n[2]);
         unsigned* dst = reinterpret_cast<unsigned*>(lds + r * C::RX);
@@ -185,14 +180,15 @@ __device__ inline int lds_axis(int li, T disp, T* w) {
 }
 
 // Interpolate from the staged region at tile-local point (lx,ly,lz) displaced by d.
-template <typename T, int DIM>
-__device__ inline T gather_lds(const T* lds, int lx, int ly, int lz, T d0, T d1, T d2) {
-    using C = Tile<T, DIM>;
+template <class C>
+__device__ inline typename C::T gather_lds(const typename C::T* lds, int lx, int ly, int lz,
+                                           typename C::T d0, typename C::T d1, typename C::T d2) {
+    using T = typename C::T;
     T wx[4], wy[4];
     const int bx = lds_axis<T, C::HALO, C::RX>(lx, d2, wx);
     const int by = lds_axis<T, C::HALO, C::RY>(ly, d1, wy);
     T acc = T(0);
-    if constexpr (DIM == 3) {
+    if constexpr (C::DIM == 3) {
         T wz[4];
         const int bz = lds_axis<T, C::HALO, C::RZ>(lz, d0, wz);
         const T* base = lds + (bz * C::RY + by) * C::RX + bx;
@@ -218,11 +214,10 @@ __device__ inline T gather_lds(const T* lds, int lx, int ly, int lz, T d0, T d1,
 }
 
 // Tile origin of this block and the local coordinates of the thread's k-th point.
-template <typename T, int DIM>
+template <class C>
 struct PointMap {
     int x0, y0, z0;
     __device__ PointMap(const Dims& dm) {
-        using C = Tile<T, DIM>;
         const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
         const int nty = (dm.n[1] + C::TY - 1) / C::TY;
         const int b = blockIdx.x;
@@ -230,10 +225,8 @@ struct PointMap {
         y0 = ((b / ntx) % nty) * C::TY;
         z0 = (b / (ntx * nty)) * C::TZ;
     }
-    // local (lx, ly, lz) of point k of this thread
     __device__ void local(int k, int& lx, int& ly, int& lz) const {
-        if constexpr (DIM == 3) {
-            using C = Tile<T, 3>;
+        if constexpr (C::DIM == 3) {
             lx = threadIdx.x % C::TX;
             ly = threadIdx.x / C::TX;
             lz = k;
@@ -245,29 +238,29 @@ struct PointMap {
     }
 };
 
-template <typename T, int DIM>
+template <class C>
 int tile_blocks(const Dims& dm) {
-    using C = Tile<T, DIM>;
     const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
     const int nty = (dm.n[1] + C::TY - 1) / C::TY;
-    const int ntz = DIM == 3 ? (dm.n[0] + C::TZ - 1) / C::TZ : 1;
+    const int ntz = C::DIM == 3 ? (dm.n[0] + C::TZ - 1) / C::TZ : 1;
     return ntx * nty * ntz;
 }
 
 // ---- semi-Lagrangian step --------------------------------------------------------
 // EPI 0: out = I[src];  1: out = fac * I[src];
 // EPI 2 (source factor, src = delta): out = 1 + sgn h/2 (I[d] + d) + h^2/2 d I[d]
-template <typename T, int DIM, int EPI>
-__global__ void __launch_bounds__(kThreads) sl_step_kernel(Dims dm, const T* __restrict__ src,
-                                                           const T* __restrict__ disp,
-                                                           const T* __restrict__ fac, T ht, T sgn,
-                                                           const int* __restrict__ bound,
-                                                           T* __restrict__ out) {
-    using C = Tile<T, DIM>;
+// `bound` >= max |disp| (cells); beyond the halo the direct gather is used.
+template <class C, int EPI>
+__global__ void __launch_bounds__(kThreads) sl_step_kernel(
+    Dims dm, const typename C::T* __restrict__ src, const typename C::T* __restrict__ disp,
+    const typename C::T* __restrict__ fac, typename C::T ht, typename C::T sgn, int bound,
+    typename C::T* __restrict__ out) {
+    using T = typename C::T;
+    constexpr int DIM = C::DIM;
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
-    const PointMap<T, DIM> pm(dm);
-    const bool use_lds = *bound <= C::HALO;
+    const PointMap<C> pm(dm);
+    const bool use_lds = bound <= C::HALO;
     const long long N = dm.N;
     // displacements of the thread's points, loaded before the staging
     T d0[C::PTS], d1[C::PTS], d2[C::PTS];
@@ -292,7 +285,7 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(Dims dm, const T* __r
             }
         }
     }
-    if (use_lds) stage<T, DIM>(dm, src, lds, pm.x0, pm.y0, pm.z0);
+    if (use_lds) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0);
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         if (!in[k]) continue;
@@ -300,7 +293,7 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(Dims dm, const T* __r
         pm.local(k, lx, ly, lz);
         T r;
         if (use_lds) {
-            r = gather_lds<T, DIM>(lds, lx, ly, lz, d0[k], d1[k], d2[k]);
+            r = gather_lds<C>(lds, lx, ly, lz, d0[k], d1[k], d2[k]);
         } else {
             r = gather_global<T, DIM>(dm, src, pm.z0 + lz, pm.y0 + ly, pm.x0 + lx, d0[k], d1[k],
                                       d2[k]);
@@ -317,27 +310,24 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(Dims dm, const T* __r
 // ---- characteristics -------------------------------------------------------------
 // dX = -(u + I[u](i - u)) / 2 (state, +v) and dY = (u + I[u](i + u)) / 2
 // (adjoint, -v), u_c = s_c v_c.  Component c of v is staged in LDS in turn;
-// the predictor points only depend on u at the grid point.  The ceil of the
-// largest |dX| / |dY| is accumulated into bound_out[0] / bound_out[1].
-template <typename T, int DIM, bool DOX, bool DOY>
+// the predictor points only depend on u at the grid point.  ubound >= max |u|.
+template <class C, bool DOX, bool DOY>
 __global__ void __launch_bounds__(kThreads) characteristics_kernel(
-    Dims dm, const T* __restrict__ v, T s0, T s1, T s2, const int* __restrict__ ubound,
-    T* __restrict__ dX, T* __restrict__ dY, int* __restrict__ bound_out) {
-    using C = Tile<T, DIM>;
+    Dims dm, const typename C::T* __restrict__ v, typename C::T s0, typename C::T s1,
+    typename C::T s2, int ubound, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
+    using T = typename C::T;
+    constexpr int DIM = C::DIM;
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
-    __shared__ int smax[2];
-    if (threadIdx.x < 2) smax[threadIdx.x] = 0;
-    const PointMap<T, DIM> pm(dm);
-    const bool use_lds = *ubound <= C::HALO;
+    const PointMap<C> pm(dm);
+    const bool use_lds = ubound <= C::HALO;
     const long long N = dm.N;
     const T s[3] = {s0, s1, s2};
-    int mx = 0, my = 0;
     for (int c = 0; c < DIM; ++c) {
         const T* vc = v + c * N;
         if (use_lds) {
             __syncthreads();
-            stage<T, DIM>(dm, vc, lds, pm.x0, pm.y0, pm.z0);
+            stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0);
         }
 #pragma unroll 1
         for (int k = 0; k < C::PTS; ++k) {
@@ -359,136 +349,158 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
                 e2 = u[1];
             }
             if (DOX) {
-                const T iv = use_lds ? gather_lds<T, DIM>(lds, lx, ly, lz, -e0, -e1, -e2)
+                const T iv = use_lds ? gather_lds<C>(lds, lx, ly, lz, -e0, -e1, -e2)
                                      : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
-                const T d = T(-0.5) * (u[c] + s[c] * iv);
-                dX[c * N + lin] = d;
-                const T ad = fabs(d);
-                mx = max(mx, ad <= T(1.0e6) ? static_cast<int>(ceil(ad)) : 1 << 30);
+                dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * iv);
             }
             if (DOY) {
-                const T iv = use_lds ? gather_lds<T, DIM>(lds, lx, ly, lz, e0, e1, e2)
+                const T iv = use_lds ? gather_lds<C>(lds, lx, ly, lz, e0, e1, e2)
                                      : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
-                const T d = T(0.5) * (u[c] + s[c] * iv);
-                dY[c * N + lin] = d;
-                const T ad = fabs(d);
-                my = max(my, ad <= T(1.0e6) ? static_cast<int>(ceil(ad)) : 1 << 30);
+                dY[c * N + lin] = T(0.5) * (u[c] + s[c] * iv);
             }
         }
     }
-    __syncthreads();
-    if (mx) atomicMax(&smax[0], mx);
-    if (my) atomicMax(&smax[1], my);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        if (DOX && smax[0]) atomicMax(&bound_out[0], smax[0]);
-        if (DOY && smax[1]) atomicMax(&bound_out[1], smax[1]);
-    }
 }
 
-// ceil(max_c max_i |s_c v_c(i)|) -> atomicMax into *out (the predictor bound).
+// max_c max_i |s_c v_c(i)| (NaN/inf counted as 1e30): FP64 block partials
 template <typename T>
-__global__ void __launch_bounds__(kThreads) velocity_bound_kernel(const T* __restrict__ v,
-                                                                  long long N, int dim, T s0, T s1,
-                                                                  T s2, int* __restrict__ out) {
+__global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restrict__ v,
+                                                                long long N, int dim, T s0, T s1,
+                                                                T s2, double* __restrict__ partial) {
     __shared__ double sh[kThreads / 64];
     const T s[3] = {s0, s1, s2};
     double m = 0.0;
     for (int c = 0; c < dim; ++c)
         for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
              i += (long long)gridDim.x * blockDim.x) {
-            double a = fabs(double(v[c * N + i] * s[c]));
-            if (!(a <= 1.0e6)) a = 1.0e6;
+            double a = fabs(double(v[c * N + i]) * double(s[c]));
+            if (!(a <= 1.0e30)) a = 1.0e30;
             m = fmax(m, a);
         }
     const double r = block_reduce<true>(m, sh);
-    if (threadIdx.x == 0) atomicMax(out, static_cast<int>(ceil(r)));
+    if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-__global__ void zero_ints_kernel(int* p, int n) {
-    if ((int)threadIdx.x < n) p[threadIdx.x] = 0;
+// Variant choice: the smallest halo that covers the bound; beyond the
+// largest the widest variant runs its direct-gather path.
+template <typename T, int DIM>
+int pick_halo(int bound) {
+    if (DIM == 2) return bound <= 4 ? 4 : 8;
+    if (sizeof(T) == 8) return bound <= 1 ? 1 : 2;
+    return bound <= 1 ? 1 : (bound <= 2 ? 2 : 4);
+}
+
+template <class C, bool DOX, bool DOY>
+void char_launch(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+                 typename C::T* dX, typename C::T* dY, hipStream_t st) {
+    using T = typename C::T;
+    characteristics_kernel<C, DOX, DOY><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+        dm, v, T(s[0]), T(s[1]), T(C::DIM == 3 ? s[2] : 0.0), ubound, dX, dY);
+}
+
+template <class C>
+void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+               typename C::T* dX, typename C::T* dY, hipStream_t st) {
+    // 3-D: one launch per direction (each keeps one gather in flight per
+    // thread); 2-D: both directions in one launch
+    if (C::DIM == 3 || !(dX && dY)) {
+        if (dX) char_launch<C, true, false>(dm, v, s, ubound, dX, dY, st);
+        if (dY) char_launch<C, false, true>(dm, v, s, ubound, dX, dY, st);
+    } else {
+        char_launch<C, true, true>(dm, v, s, ubound, dX, dY, st);
+    }
+}
+
+template <class C>
+void step_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
+                 const typename C::T* fac, int bound, typename C::T* out, hipStream_t st) {
+    using T = typename C::T;
+    if (fac)
+        sl_step_kernel<C, 1><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+            dm, src, disp, fac, T(0), T(0), bound, out);
+    else
+        sl_step_kernel<C, 0><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+            dm, src, disp, fac, T(0), T(0), bound, out);
+}
+
+template <class C>
+void factor_launch(const Dims& dm, const typename C::T* delta, const typename C::T* disp,
+                   double ht, double sgn, int bound, typename C::T* out, hipStream_t st) {
+    using T = typename C::T;
+    sl_step_kernel<C, 2><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+        dm, delta, disp, nullptr, T(ht), T(sgn), bound, out);
+}
+
+// Calls f(Tile<...>{}) with the variant chosen for `bound`.
+template <typename T, typename F>
+void dispatch_tile(const Dims& dm, int bound, F&& f) {
+    if (dm.dim == 3) {
+        const int h = pick_halo<T, 3>(bound);
+        if (h == 1) f(Tile<T, 3, 1>{});
+        else if (h == 2 || sizeof(T) == 8) f(Tile<T, 3, 2>{});
+        else f(Tile<T, 3, 4>{});
+    } else {
+        if (pick_halo<T, 2>(bound) == 4) f(Tile<T, 2, 4>{});
+        else f(Tile<T, 2, 8>{});
+    }
 }
 
 }  // namespace
 
-template <typename T>
-hipError_t launch_zero_bounds(int* bounds, int n, hipStream_t st) {
-    zero_ints_kernel<<<1, 64, 0, st>>>(bounds, n);
-    return hipGetLastError();
+int displacement_bound(double umax, int dim) {
+    // |X| = |u(i) + I[u](xi*)| / 2 <= (1 + 1.25^d) max|u| / 2: the cubic
+    // Lagrange weights have absolute sum at most 1.25 per axis
+    if (!(umax <= 1.0e6)) return 1 << 20;
+    const double f = 0.5 * (1.0 + std::pow(1.25, dim));
+    return static_cast<int>(std::ceil(f * umax * (1.0 + 1e-6)));
 }
 
 template <typename T>
-hipError_t launch_velocity_bound(const Dims& dm, const T* v, const double* s, int* out,
-                                 hipStream_t st) {
+hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, double* partial,
+                               double* res, hipStream_t st) {
     const int nb = reduction_blocks(dm.N);
-    velocity_bound_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, T(s[0]), T(s[1]),
-                                                      T(dm.dim == 3 ? s[2] : 0.0), out);
-    return hipGetLastError();
-}
-
-template <typename T, int DIM, bool DOX, bool DOY>
-void char_launch(const Dims& dm, const T* v, const double* s, const int* ubound, T* dX, T* dY,
-                 int* bound_out, hipStream_t st) {
-    characteristics_kernel<T, DIM, DOX, DOY>
-        <<<tile_blocks<T, DIM>(dm), kThreads, tile_lds_bytes<T, DIM>(), st>>>(
-            dm, v, T(s[0]), T(s[1]), T(DIM == 3 ? s[2] : 0.0), ubound, dX, dY, bound_out);
-}
-
-// 3-D: one launch per direction (each stages the components of v again but
-// keeps one gather in flight per thread); 2-D: both directions in one launch.
-template <typename T>
-hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, const int* ubound,
-                                  T* dX, T* dY, int* bound_out, hipStream_t st) {
-    if (dm.dim == 3) {
-        if (dX) char_launch<T, 3, true, false>(dm, v, s, ubound, dX, dY, bound_out, st);
-        if (dY) char_launch<T, 3, false, true>(dm, v, s, ubound, dX, dY, bound_out, st);
-    } else {
-        if (dX && dY) char_launch<T, 2, true, true>(dm, v, s, ubound, dX, dY, bound_out, st);
-        else if (dX) char_launch<T, 2, true, false>(dm, v, s, ubound, dX, dY, bound_out, st);
-        else if (dY) char_launch<T, 2, false, true>(dm, v, s, ubound, dX, dY, bound_out, st);
-    }
+    velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, T(s[0]), T(s[1]),
+                                                    T(dm.dim == 3 ? s[2] : 0.0), partial);
+    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 1, res);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac,
-                          const int* bound, T* out, hipStream_t st) {
-    if (dm.dim == 3) {
-        const dim3 g(tile_blocks<T, 3>(dm));
-        const size_t lds = tile_lds_bytes<T, 3>();
-        if (fac) sl_step_kernel<T, 3, 1><<<g, kThreads, lds, st>>>(dm, src, disp, fac, T(0), T(0), bound, out);
-        else sl_step_kernel<T, 3, 0><<<g, kThreads, lds, st>>>(dm, src, disp, fac, T(0), T(0), bound, out);
-    } else {
-        const dim3 g(tile_blocks<T, 2>(dm));
-        const size_t lds = tile_lds_bytes<T, 2>();
-        if (fac) sl_step_kernel<T, 2, 1><<<g, kThreads, lds, st>>>(dm, src, disp, fac, T(0), T(0), bound, out);
-        else sl_step_kernel<T, 2, 0><<<g, kThreads, lds, st>>>(dm, src, disp, fac, T(0), T(0), bound, out);
-    }
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int ubound, T* dX,
+                                  T* dY, hipStream_t st) {
+    dispatch_tile<T>(dm, ubound, [&](auto tile) {
+        char_dirs<decltype(tile)>(dm, v, s, ubound, dX, dY, st);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int bound,
+                          T* out, hipStream_t st) {
+    dispatch_tile<T>(dm, bound, [&](auto tile) {
+        step_launch<decltype(tile)>(dm, src, disp, fac, bound, out, st);
+    });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, const int* bound, T* out, hipStream_t st) {
-    if (dm.dim == 3)
-        sl_step_kernel<T, 3, 2><<<tile_blocks<T, 3>(dm), kThreads, tile_lds_bytes<T, 3>(), st>>>(
-            dm, delta, disp, nullptr, T(ht), T(sgn), bound, out);
-    else
-        sl_step_kernel<T, 2, 2><<<tile_blocks<T, 2>(dm), kThreads, tile_lds_bytes<T, 2>(), st>>>(
-            dm, delta, disp, nullptr, T(ht), T(sgn), bound, out);
+                                double sgn, int bound, T* out, hipStream_t st) {
+    dispatch_tile<T>(dm, bound, [&](auto tile) {
+        factor_launch<decltype(tile)>(dm, delta, disp, ht, sgn, bound, out, st);
+    });
     return hipGetLastError();
 }
 
 #define GAN_INST(T)                                                                               \
-    template hipError_t launch_zero_bounds<T>(int*, int, hipStream_t);                            \
-    template hipError_t launch_velocity_bound<T>(const Dims&, const T*, const double*, int*,      \
-                                                 hipStream_t);                                    \
-    template hipError_t launch_characteristics<T>(const Dims&, const T*, const double*,           \
-                                                  const int*, T*, T*, int*, hipStream_t);         \
-    template hipError_t launch_sl_step<T>(const Dims&, const T*, const T*, const T*, const int*,  \
-                                          T*, hipStream_t);                                       \
+    template hipError_t launch_velocity_max<T>(const Dims&, const T*, const double*, double*,     \
+                                               double*, hipStream_t);                             \
+    template hipError_t launch_characteristics<T>(const Dims&, const T*, const double*, int, T*,  \
+                                                  T*, hipStream_t);                               \
+    template hipError_t launch_sl_step<T>(const Dims&, const T*, const T*, const T*, int, T*,     \
+                                          hipStream_t);                                           \
     template hipError_t launch_source_factor<T>(const Dims&, const T*, const T*, double, double,  \
-                                                const int*, T*, hipStream_t);
+                                                int, T*, hipStream_t);
 GAN_INST(float)
 GAN_INST(double)
 #undef GAN_INST

@@ -120,24 +120,77 @@ def algorithmic_bytes(kernel, wl, N, s):
     return None
 
 
-def cpu_baseline(synth_mod):
+def cpu_baseline(synth_mod, min_seconds=10.0):
     """The FP64 oracle's gradient on the same recipe at 64^3 (1/8 of the
-    points), scaled to the 128^3 workload by the point count."""
-    import numpy as np
+    points), repeated for at least min_seconds, scaled to the 128^3 workload
+    by the point count."""
     from oracle.transport import TransportProblem
     wl = synth_mod.workload("c2", shape=(64, 64, 64))
     gen = TransportProblem(wl.m0, wl.m0, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
     m1 = gen.forward(wl.vstar)[-1]
     P = TransportProblem(wl.m0, m1, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
     v = 0.5 * wl.vstar
+    reps = 0
     t0 = time.perf_counter()
-    P.gradient(v)
-    t = time.perf_counter() - t0
+    while True:
+        P.gradient(v)
+        reps += 1
+        t = time.perf_counter() - t0
+        if t >= min_seconds:
+            break
     scale = (128 ** 3) / (64 ** 3)
-    return {"value": round(1.0 / (t * scale), 6), "unit": "grad evals/s", "cores": 1,
+    per = t / reps
+    return {"value": round(1.0 / (per * scale), 6), "unit": "grad evals/s", "cores": 1,
             "kind": "oracle",
-            "sample": f"one oracle gradient of the 128^3 recipe at 64^3 ({t:.1f} s, numpy, "
-                      f"single thread), time scaled x{scale:.0f} by grid points"}
+            "sample": f"{reps} oracle gradients of the 128^3 recipe at 64^3 ({t:.1f} s, numpy, "
+                      f"single thread), time per gradient scaled x{scale:.0f} by grid points"}
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE
+    summary of `kernel`, or None when its source changed since the counters
+    were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_c2_128cubed_traffic.txt")
+    src = os.path.join(ROOT, "paper_2510_08782_amd", "csrc",
+                       {"sl_step": "sl.hip", "deriv_axis": "spectral.hip"}.get(kernel, ""))
+    if not (os.path.exists(path) and os.path.isfile(src)):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line:
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if kv.get("source_sha256_16") != digest:
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
+
+
+def c3_throughput(torch, gan, synth):
+    """256^3 advection, H2, nt=8: FP32 with checkpointed history (every 2nd
+    state) against the plain FP64 path: grad evals/s and device workspace."""
+    wl = synth.workload("c3")
+    out = {}
+    for name, dtype, ck in (("fp32_checkpoint2", torch.float32, 2), ("fp64_plain", torch.float64, 1)):
+        dev = lambda x: torch.tensor(x, dtype=dtype, device="cuda")
+        m0 = dev(wl.m0)
+        vstar = dev(wl.vstar)
+        gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=ck)
+        gen.eval_objective(vstar)
+        m1 = gen.get_field("state", wl.nt)
+        gen.close()
+        P = gan.Problem(m0, m1, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=ck)
+        v = (0.5 * vstar).contiguous()
+        torch.cuda.reset_peak_memory_stats()
+        t = time_gradients(torch, P, v, 5)
+        out[name] = {"grad_evals_per_s": round(1.0 / t, 2), "ms_per_grad": round(1e3 * t, 3),
+                     "workspace_bytes": P.workspace_bytes(),
+                     "torch_peak_bytes": int(torch.cuda.max_memory_allocated())}
+        P.close()
+        del m0, m1, vstar, v
+        torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -148,6 +201,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-c3", action="store_true", help="skip the 256^3 throughput figures")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -195,7 +249,7 @@ def main():
         achieved = bpl / (avg_ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1),
                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "avg_launch_us": round(avg_ms * 1e3, 2),
+                    "traffic": measured_traffic(dname), "avg_launch_us": round(avg_ms * 1e3, 2),
                     "bytes_per_launch": bpl, "launches": dcount}
     kernels = {k: {"ms": round(ms, 3), "launches": c,
                    "avg_us": round(1e3 * ms / c, 2) if c else None,
@@ -227,6 +281,10 @@ def main():
             log("time-to-1e-2, FP64 GA-NGMRES")
             extra["tts_fp64_ga_ngmres"] = time_to_solution(torch, P64, params)
         P64.close()
+
+    if not args.no_c3:
+        log("256^3 throughput (c3)")
+        extra["c3_256cubed"] = c3_throughput(torch, gan, synth)
 
     cpu = None
     if not args.no_cpu:

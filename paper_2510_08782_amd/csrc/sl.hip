@@ -84,9 +84,11 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
             acc += w0[a] * sa;
         }
     } else {
+        // 2-D: axis 0 indexes independent slices
+        const T* sl = s + (long long)i0 * dm.n[1] * dm.n[2];
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const T* row = s + o1[b];
+            const T* row = sl + o1[b];
             acc += w1[b] * (w2[0] * row[o2[0]] + w2[1] * row[o2[1]] + w2[2] * row[o2[2]] +
                             w2[3] * row[o2[3]]);
         }
@@ -156,7 +158,8 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
     for (int r = wave; r < ROWS; r += NW) {
         const int ry = r % C::RY, rz = r / C::RY;
         const int gy = wrapn(y0 - C::HALO - 1 + ry, dm.n[1]);
-        const int gz = C::DIM == 3 ? wrapn(z0 - C::HALO - 1 + rz, dm.n[0]) : 0;
+        // 2-D: axis 0 indexes independent slices (no interpolation across it)
+        const int gz = C::DIM == 3 ? wrapn(z0 - C::HALO - 1 + rz, dm.n[0]) : z0;
         // N < 2^31 elements
         const unsigned* row = reinterpret_cast<const unsigned*>(src + (gz * dm.n[1] + gy) * dm.n[2]);
         unsigned* dst = reinterpret_cast<unsigned*>(lds + r * C::RX);
@@ -192,6 +195,25 @@ __device__ inline typename C::T gather_lds(const typename C::T* lds, int lx, int
         T wz[4];
         const int bz = lds_axis<T, C::HALO, C::RZ>(lz, d0, wz);
         const T* base = lds + (bz * C::RY + by) * C::RX + bx;
+#ifdef GAN_SL_PRELOAD
+        T val[64];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) val[(a * 4 + b) * 4 + c] = base[(a * C::RY + b) * C::RX + c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            T sa = T(0);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const T* row = val + (a * 4 + b) * 4;
+                sa += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+            }
+            acc += wz[a] * sa;
+        }
+#else
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             T sa = T(0);
@@ -202,6 +224,7 @@ __device__ inline typename C::T gather_lds(const typename C::T* lds, int lx, int
             }
             acc += wz[a] * sa;
         }
+#endif
     } else {
         const T* base = lds + by * C::RX + bx;
 #pragma unroll
@@ -213,17 +236,36 @@ __device__ inline typename C::T gather_lds(const typename C::T* lds, int lx, int
     return acc;
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b mod 8), each with its own L2.  Tiles are numbered x-fastest, then y,
+// then z, and XCD k is given the contiguous range of tiles
+// [k ceil(T/8), (k+1) ceil(T/8)): a slab whose halos are mostly read from
+// the same L2 instead of once per XCD.
+constexpr int kXcds = 8;
+
+template <class C>
+__host__ __device__ inline int tile_count(const Dims& dm) {
+    const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
+    const int nty = (dm.n[1] + C::TY - 1) / C::TY;
+    const int ntz = C::DIM == 3 ? (dm.n[0] + C::TZ - 1) / C::TZ : dm.n[0];
+    return ntx * nty * ntz;
+}
+
 // Tile origin of this block and the local coordinates of the thread's k-th point.
 template <class C>
 struct PointMap {
     int x0, y0, z0;
+    bool valid;
     __device__ PointMap(const Dims& dm) {
         const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
         const int nty = (dm.n[1] + C::TY - 1) / C::TY;
-        const int b = blockIdx.x;
-        x0 = (b % ntx) * C::TX;
-        y0 = ((b / ntx) % nty) * C::TY;
-        z0 = (b / (ntx * nty)) * C::TZ;
+        const int T = tile_count<C>(dm);
+        const int per = (T + kXcds - 1) / kXcds;
+        const int t = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+        valid = t < T;
+        x0 = (t % ntx) * C::TX;
+        y0 = ((t / ntx) % nty) * C::TY;
+        z0 = (t / (ntx * nty)) * C::TZ;
     }
     __device__ void local(int k, int& lx, int& ly, int& lz) const {
         if constexpr (C::DIM == 3) {
@@ -240,10 +282,8 @@ struct PointMap {
 
 template <class C>
 int tile_blocks(const Dims& dm) {
-    const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
-    const int nty = (dm.n[1] + C::TY - 1) / C::TY;
-    const int ntz = C::DIM == 3 ? (dm.n[0] + C::TZ - 1) / C::TZ : 1;
-    return ntx * nty * ntz;
+    const int T = tile_count<C>(dm);
+    return kXcds * ((T + kXcds - 1) / kXcds);
 }
 
 // ---- semi-Lagrangian step --------------------------------------------------------
@@ -260,6 +300,7 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
     const PointMap<C> pm(dm);
+    if (!pm.valid) return;
     const bool use_lds = bound <= C::HALO;
     const long long N = dm.N;
     // displacements of the thread's points, loaded before the staging
@@ -320,6 +361,7 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
     const PointMap<C> pm(dm);
+    if (!pm.valid) return;
     const bool use_lds = ubound <= C::HALO;
     const long long N = dm.N;
     const T s[3] = {s0, s1, s2};

@@ -7,6 +7,8 @@ Paper, Sec. 2.3:
     halving rho until it holds; rho is kept between iterations and doubled
     for the next iteration when the first trial is accepted;
   * fixed-point map q(v) = v + rho s                         (eq. e:fixedpoint)
+  * AA(w) (Alg. 2) and its alternating form GA-AA(w; sigma, tau), driven by
+    ga_aa below;
   * NGMRES(w) (Alg. 1) and GA-NGMRES(w; sigma, tau) (Alg. 3): with
     w_k = min(k, w) and r = g(q(v^k)),
         beta = argmin || r + sum_{i=0}^{w_k} beta_i (r - g(v^{k-i})) ||_2
@@ -190,6 +192,59 @@ def ga_ngmres(grad, qmap, v0, w, sigma, tau, eps_rel, n_iter, variant="GA",
     return res
 
 
+def ga_aa(grad, qmap, v0, w, sigma, tau, eps_rel, n_iter, variant="GA",
+          lsq=lsq_from_gram, keep_iterates=False):
+    """Generic GA-AA(w; sigma, tau): Alg. 2 (Anderson acceleration) with the
+    alternation of Alg. 3.  With r^k = v^k - q(v^k) and w_k = min(k, w),
+        xi = argmin || r^k + sum_{i=1}^{w_k} xi_i (r^k - r^{k-i}) ||_2
+        v^{k+1} = q(v^k) + sum_i xi_i (q(v^k) - q(v^{k-i}));
+    an iteration is a plain fixed-point step v^{k+1} = q(v^k) when the switch
+    of Alg. 3 says so, and when w_k = 0.  The pairs (r, q) of the last w
+    iterations are kept."""
+    v = np.array(v0, dtype=np.float64)
+    J, g = grad(v)
+    n_grad = 1
+    g0 = float(np.max(np.abs(g)))
+    hist = []                            # (r, q), most recent last, at most w
+    res = Result(v=v, J=J, g=g, iterations=0, g0inf=g0)
+    if keep_iterates:
+        res.iterates.append(v.copy())
+    k = 0
+    while True:
+        wk = min(k, w)
+        q, info = qmap(v, J, g)
+        r = v - q
+        fp = sigma == 0 or is_fp_step(k, sigma, tau, variant) or wk == 0
+        xi = None
+        if fp:
+            vn = q
+            J, g = grad(vn)
+            n_grad += 1
+        else:
+            window = hist[::-1][:wk]          # i = 1..w_k : (r^{k-i}, q^{k-i})
+            xi = lsq(gram([r] + [rp for rp, _ in window]))
+            vn = q.copy()
+            for c, (_, qp) in zip(xi, window):
+                vn = vn + c * (q - qp)
+            J, g = grad(vn)
+            n_grad += 1
+        hist.append((r, q))
+        if len(hist) > w:
+            hist.pop(0)
+        v = vn
+        k += 1
+        ginf = float(np.max(np.abs(g)))
+        res.records.append(Record(k, "fp" if fp else "aa", J, ginf, xi,
+                                  info.get("rho"), info.get("trials", 0)))
+        if keep_iterates:
+            res.iterates.append(v.copy())
+        if ginf <= eps_rel * g0 or k >= n_iter:
+            break
+    res.v, res.J, res.g, res.iterations = v, J, g, k
+    res.n_grad = n_grad
+    return res
+
+
 class LineSearchMap:
     """q(v) = v - rho (alpha L)^-1 g(v) with Armijo backtracking and rho memory."""
 
@@ -210,11 +265,13 @@ class LineSearchMap:
 
 
 def solve(problem, w=5, sigma=2, tau=1, eps_rel=1e-2, n_iter=200, variant="GA",
-          v0=None, keep_iterates=False):
-    """GA-NGMRES on the transport problem starting from v0 (default 0)."""
+          v0=None, keep_iterates=False, accel="ngmres"):
+    """GA-NGMRES (accel="ngmres") or GA-AA (accel="aa") on the transport
+    problem starting from v0 (default 0)."""
     v0 = np.zeros((problem.grid.d,) + problem.grid.shape) if v0 is None else v0
     qmap = LineSearchMap(problem)
-    res = ga_ngmres(problem.gradient, qmap, v0, w, sigma, tau, eps_rel, n_iter,
-                    variant=variant, keep_iterates=keep_iterates)
+    driver = {"ngmres": ga_ngmres, "aa": ga_aa}[accel]
+    res = driver(problem.gradient, qmap, v0, w, sigma, tau, eps_rel, n_iter,
+                 variant=variant, keep_iterates=keep_iterates)
     res.n_obj = qmap.n_obj
     return res

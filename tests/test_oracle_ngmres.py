@@ -167,3 +167,31 @@ def test_determinism_and_descent():
     np.testing.assert_array_equal(a.v, b.v)
     assert a.records[-1].ginf < 0.2 * a.g0inf
     assert a.records[-1].J < P.objective(np.zeros_like(a.v))
+
+
+# -- Anderson acceleration (Alg. 2) and GA-AA -----------------------------------
+def test_aa_infinite_window_is_q_of_gmres():
+    """Linear case: the AA iterate v^{k+1} equals q applied to the k-step GMRES
+    iterate (Sec. 2.3)."""
+    A, b, grad, qmap = linear_backend(seed=7)
+    x0 = np.zeros_like(b)
+    res = ng.ga_aa(grad, qmap, x0, w=100, sigma=1, tau=0, eps_rel=1e-14, n_iter=10,
+                   keep_iterates=True)
+    for k in range(1, 10):
+        xk = gmres_bruteforce(A, b, x0, k)
+        qx = xk - (A @ xk - b)
+        np.testing.assert_allclose(res.iterates[k + 1], qx, atol=1e-10 * np.abs(qx).max())
+
+
+def test_aa_switch_and_window_semantics():
+    P = _small_problem()
+    res = ng.solve(P, w=3, sigma=2, tau=1, eps_rel=1e-12, n_iter=7, accel="aa")
+    # k = 0 has an empty window: a plain fixed-point step
+    assert [r.kind for r in res.records] == ["fp", "aa", "fp", "aa", "aa", "fp", "aa"]
+    a = ng.solve(P, w=5, sigma=2, tau=1, eps_rel=1e-12, n_iter=5, accel="aa")
+    b = ng.solve(P, w=40, sigma=2, tau=1, eps_rel=1e-12, n_iter=5, accel="aa")
+    np.testing.assert_array_equal(a.v, b.v)
+    # w = 0: every step is the line-searched fixed-point step (RPGD)
+    c = ng.solve(P, w=0, sigma=1, tau=0, eps_rel=1e-12, n_iter=4, accel="aa")
+    d = ng.solve(P, w=0, sigma=0, tau=1, eps_rel=1e-12, n_iter=4)
+    np.testing.assert_array_equal(c.v, d.v)

@@ -55,7 +55,8 @@ enum {
 enum { GANMRES_ADVECTION = 0, GANMRES_CONTINUITY = 1 };
 enum { GANMRES_F32 = 0, GANMRES_F64 = 1 };
 enum { GANMRES_VARIANT_GA = 0, GANMRES_VARIANT_ALT = 1 };
-enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1 };
+enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1, GANMRES_STEP_AA = 2 };
+enum { GANMRES_ACCEL_NGMRES = 0, GANMRES_ACCEL_AA = 1 };
 
 typedef struct ganmres_handle ganmres_handle;
 
@@ -83,13 +84,16 @@ typedef struct {
     double rho_cap;        /* cap on the stored step, <= 0 means none           */
     int variant;           /* GANMRES_VARIANT_GA: FP when mod(k,s+t) >= sigma;
                               GANMRES_VARIANT_ALT: FP when mod(k,s+t) < tau     */
+    int accel;             /* GANMRES_ACCEL_NGMRES (Alg. 1/3) or GANMRES_ACCEL_AA
+                              (Anderson acceleration, Alg. 2, with the same
+                              alternation: GA-AA)                               */
 } ganmres_solver_params;
 
 #define GANMRES_MAX_WINDOW 64
 
 typedef struct {
     int k;                 /* iterations completed after this call              */
-    int step_kind;         /* GANMRES_STEP_NGMRES or GANMRES_STEP_FP            */
+    int step_kind;         /* GANMRES_STEP_NGMRES, GANMRES_STEP_AA or _FP       */
     int stop;              /* 1 when the stopping rule of Alg. 3 holds          */
     int n_trials;          /* objective evaluations in this line search         */
     int n_grad;            /* gradient evaluations in this call                 */
@@ -143,13 +147,16 @@ int ganmres_eval_gradient(ganmres_handle* h, const void* v, void* g,
  * velocities (may alias).  gs: host, nullable: <g, s>_h. */
 int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs);
 
-/* One iteration k of GA-NGMRES(w; sigma, tau) (Alg. 3) around the line-searched
- * map q(v) = v + rho s (eqs. e:linesearch, e:armijo).  v: device velocity, in:
- * v^k, out: v^{k+1}.  On the first call after create or reset, v is v^0 and
- * g(v^0) is evaluated first.  The handle keeps k, the stored step rho, the
- * last w+1 pairs (v, g) and ||g(v^0)||_inf.  info: host, nullable.
+/* One iteration k of GA-NGMRES(w; sigma, tau) (Alg. 3), or of GA-AA with
+ * accel = GANMRES_ACCEL_AA (Alg. 2 with the alternation of Alg. 3), around the
+ * line-searched map q(v) = v + rho s (eqs. e:linesearch, e:armijo).  v: device
+ * velocity, in: v^k, out: v^{k+1}.  On the first call after create or reset, v
+ * is v^0 and g(v^0) is evaluated first.  The handle keeps k, the stored step
+ * rho, the window (the last w+1 pairs (v, g), or the last w pairs
+ * (v - q(v), q(v)) for AA) and ||g(v^0)||_inf.  info: host, nullable.
  * Errors: GANMRES_EINVAL (w < 0 or > GANMRES_MAX_WINDOW, sigma = tau = 0,
- * negative counts), GANMRES_ELINESEARCH, GANMRES_ELSQ, GANMRES_ENONFINITE. */
+ * negative counts, unknown accel, accel or w changed without a reset),
+ * GANMRES_ELINESEARCH, GANMRES_ELSQ, GANMRES_ENONFINITE. */
 int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info);
 

@@ -23,7 +23,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ganmres.h")
 ADVECTION, CONTINUITY = 0, 1
 F32, F64 = 0, 1
 VARIANT_GA, VARIANT_ALT = 0, 1
-STEP_NGMRES, STEP_FP = 0, 1
+STEP_NGMRES, STEP_FP, STEP_AA = 0, 1, 2
+ACCEL_NGMRES, ACCEL_AA = 0, 1
 MAX_WINDOW = 64
 
 ERRORS = {
@@ -50,7 +51,7 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int), ("sigma", ctypes.c_int), ("tau", ctypes.c_int),
                 ("eps_rel", ctypes.c_double), ("n_iter", ctypes.c_int),
                 ("c_armijo", ctypes.c_double), ("max_backtracks", ctypes.c_int),
-                ("rho_cap", ctypes.c_double), ("variant", ctypes.c_int)]
+                ("rho_cap", ctypes.c_double), ("variant", ctypes.c_int), ("accel", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -112,10 +113,12 @@ class SolveParams:
     max_backtracks: int = 30
     rho_cap: float = 0.0
     variant: int = VARIANT_GA
+    accel: int = ACCEL_NGMRES
 
     def to_c(self):
         return SolverParams(self.w, self.sigma, self.tau, self.eps_rel, self.n_iter,
-                            self.c_armijo, self.max_backtracks, self.rho_cap, self.variant)
+                            self.c_armijo, self.max_backtracks, self.rho_cap, self.variant,
+                            self.accel)
 
 
 class Problem:
@@ -235,7 +238,8 @@ class Problem:
         return out
 
     def solve(self, params: SolveParams, v0=None, callback=None):
-        """Run GA-NGMRES from v0 (default 0) until the stopping rule holds."""
+        """Run GA-NGMRES, or GA-AA when params.accel is ACCEL_AA, from v0
+        (default 0) until the stopping rule holds."""
         v = self.new_velocity() if v0 is None else self._vec(v0).clone()
         self.reset()
         infos = []

@@ -252,6 +252,9 @@ class Problem : public ProblemBase {
     int wcap = -1;
     std::vector<std::unique_ptr<DevBuf>> ring_v, ring_g;
     std::unique_ptr<DevBuf> qb, gqb, sb;
+    std::vector<std::unique_ptr<DevBuf>> aa_r, aa_q;  // GA-AA: (r, q) history
+    int aa_cur = 0;
+    int acc_cap = -1;
     std::deque<int> hist;
     bool started = false;
     int k = 0;
@@ -386,6 +389,8 @@ class Problem : public ProblemBase {
         long long s = ws_bytes;
         for (auto& r : ring_v) s += r->bytes;
         for (auto& r : ring_g) s += r->bytes;
+        for (auto& r : aa_r) s += r->bytes;
+        for (auto& r : aa_q) s += r->bytes;
         if (qb) s += qb->bytes + gqb->bytes + sb->bytes;
         return s;
     }
@@ -744,17 +749,30 @@ class Problem : public ProblemBase {
 
     T* rv(int slot) { return static_cast<T*>(ring_v[slot]->p); }
     T* rg(int slot) { return static_cast<T*>(ring_g[slot]->p); }
+    T* ar(int slot) { return static_cast<T*>(aa_r[slot]->p); }
+    T* aq(int slot) { return static_cast<T*>(aa_q[slot]->p); }
 
-    void ensure_solver(int w) {
-        if (wcap == w) return;
-        if (started) throw Error(GANMRES_EINVAL, "window changed during a solve; reset first");
+    // NGMRES keeps w+1 pairs (v, g) plus one being formed; AA keeps the current
+    // and next (v, g) and w+1 pairs (r, q).
+    void ensure_solver(int w, int acc) {
+        if (wcap == w && acc_cap == acc) return;
+        if (started) throw Error(GANMRES_EINVAL, "window or accelerator changed during a solve; reset first");
+        const bool aa = acc == GANMRES_ACCEL_AA;
         ring_v.clear();
         ring_g.clear();
-        for (int i = 0; i < w + 2; ++i) {
+        for (int i = 0; i < (aa ? 2 : w + 2); ++i) {
             ring_v.emplace_back(new DevBuf);
             ring_v.back()->alloc(sizeof(T) * d * N);
             ring_g.emplace_back(new DevBuf);
             ring_g.back()->alloc(sizeof(T) * d * N);
+        }
+        aa_r.clear();
+        aa_q.clear();
+        for (int i = 0; i < (aa ? w + 1 : 0); ++i) {
+            aa_r.emplace_back(new DevBuf);
+            aa_r.back()->alloc(sizeof(T) * d * N);
+            aa_q.emplace_back(new DevBuf);
+            aa_q.back()->alloc(sizeof(T) * d * N);
         }
         qb.reset(new DevBuf);
         qb->alloc(sizeof(T) * d * N);
@@ -763,6 +781,7 @@ class Problem : public ProblemBase {
         sb.reset(new DevBuf);
         sb->alloc(sizeof(T) * d * N);
         wcap = w;
+        acc_cap = acc;
     }
 
     static bool is_fp(int k, const ganmres_solver_params& p) {
@@ -771,48 +790,33 @@ class Problem : public ProblemBase {
         return p.variant == GANMRES_VARIANT_ALT ? (m < p.tau) : (m >= p.sigma);
     }
 
-    void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) override {
-        ensure_solver(p.w);
-        info = ganmres_step_info{};
-        int ngrad = 0;
-        if (!started) {
-            HIPCHK(hipMemcpyAsync(rv(0), v, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
-            Jcur = gradient(rv(0), rg(0), false);
-            ++ngrad;
-            g0inf = maxabs(rg(0));
-            if (!std::isfinite(Jcur) || !std::isfinite(g0inf))
-                throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient at v^0");
-            hist.assign(1, 0);
-            k = 0;
-            rho_bar = 1.0;
-            started = true;
-        }
-        const int cur = hist.back();
+    // Armijo line search from the current iterate (Vc, Gc, Jcur); the accepted
+    // trial is left in qb with its forward solve kept (eqs. e:rpgd, e:armijo).
+    // Along the line the regulariser is a quadratic in rho:
+    // R(v + rho s) = R(v) + 2 rho <v,L s>_h + rho^2 <s,L s>_h, and the spectrum
+    // of the accepted trial is v^ + rho s^; trials need no transform of their own.
+    double line_search(T* Vc, T* Gc, const ganmres_solver_params& p, ganmres_step_info& info,
+                       double& Jq) {
         T* q = static_cast<T*>(qb->p);
-        T* gq = static_cast<T*>(gqb->p);
         T* s = static_cast<T*>(sb->p);
-        // direction and line search (eqs. e:rpgd, e:armijo).  Along the line the
-        // regulariser is a quadratic in rho: R(v + rho s) = R(v) + 2 rho <v,L s>_h
-        // + rho^2 <s,L s>_h, and the spectrum of the accepted trial is
-        // v^ + rho s^; trials therefore need no transform of their own.
-        if (vh_of != rv(cur)) {
-            spectrum_of(rv(cur));
+        if (vh_of != Vc) {
+            spectrum_of(Vc);
             HIPCHK(hipMemcpyAsync(hres, dres + 64, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipStreamSynchronize(st));
             reg_cached = cell / double(N) * hres[0];
         }
-        if (umax_of != rv(cur)) set_bounds(rv(cur), velocity_max(rv(cur)));
+        if (umax_of != Vc) set_bounds(Vc, velocity_max(Vc));
         const double R0 = reg_cached, um0 = umax;
-        const double gs = precond_keep(rg(cur), s, true);
+        const double gs = precond_keep(Gc, s, true);
         run(KC_REDUCE, [&] { return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres, st); });
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const double cA = cell / double(N) * hres[0], cB = cell / double(N) * hres[1];
-        double rho = rho_bar, Jq = 0.0, Rq = R0;
+        double rho = rho_bar, Rq = R0;
         int trials = 0;
         bool accepted = false;
         for (int t = 0; t <= p.max_backtracks; ++t) {
-            run(KC_VEC, [&] { return launch_axpy<T>(rv(cur), rho, s, q, d * N, st); });
+            run(KC_VEC, [&] { return launch_axpy<T>(Vc, rho, s, q, d * N, st); });
             Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
             Jq = objective_trial(q, Rq, um0 + rho * smax);
             ++trials;
@@ -830,63 +834,40 @@ class Problem : public ProblemBase {
         vh_of = q;
         reg_cached = Rq;
         reg_from_device = false;
-        const double Jq_grad = gradient(q, gq, true);
-        (void)Jq_grad;
-        ++ngrad;
-        // the free slot (not in the window)
-        int slot = -1;
-        for (int i = 0; i < (int)ring_v.size(); ++i)
-            if (std::find(hist.begin(), hist.end(), i) == hist.end()) {
-                slot = i;
-                break;
-            }
-        const bool fp = is_fp(k, p);
-        double Jnew;
-        if (fp) {
-            std::swap(ring_v[slot], qb);
-            std::swap(ring_g[slot], gqb);
-            Jnew = Jq;
-            info.step_kind = GANMRES_STEP_FP;
+        return rho;
+    }
+
+    // least-squares coefficients from the FP64 Gram matrix of vecs[0..K)
+    std::vector<double> gram_lsq(const std::vector<const T*>& vecs) {
+        const int K = (int)vecs.size();
+        std::vector<double> G(K * K);
+        if (K <= 8) {
+            run(KC_REDUCE, [&] { return launch_gram<T>(vecs.data(), K, d * N, partial, dres, st); });
+            const int np = K * (K + 1) / 2;
+            HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * np, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+            int qi = 0;
+            for (int a = 0; a < K; ++a)
+                for (int bb = a; bb < K; ++bb) G[a * K + bb] = G[bb * K + a] = hres[qi++];
         } else {
-            const int wk = std::min(k, p.w);
-            const int K = wk + 2;
-            std::vector<const T*> vecs(K);
-            vecs[0] = gq;
-            for (int i = 0; i <= wk; ++i) vecs[i + 1] = rg(hist[hist.size() - 1 - i]);
-            std::vector<double> G(K * K);
-            if (K <= 8) {
-                run(KC_REDUCE, [&] { return launch_gram<T>(vecs.data(), K, d * N, partial, dres, st); });
-                const int np = K * (K + 1) / 2;
-                HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * np, hipMemcpyDeviceToHost, st));
-                HIPCHK(hipStreamSynchronize(st));
-                int qi = 0;
-                for (int a = 0; a < K; ++a)
-                    for (int bb = a; bb < K; ++bb) G[a * K + bb] = G[bb * K + a] = hres[qi++];
-            } else {
-                for (int a = 0; a < K; ++a)
-                    for (int bb = a; bb < K; ++bb) {
-                        run(KC_REDUCE, [&] { return launch_dot<T>(vecs[a], vecs[bb], d * N, partial, dres, st); });
-                        G[a * K + bb] = G[bb * K + a] = fetch();
-                    }
-            }
-            std::vector<double> beta = lsq_from_gram(K, G);
-            for (double x : beta)
-                if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
-            std::vector<const T*> xs(wk + 1);
-            for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
-            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), beta.data(), wk + 1, rv(slot), d * N, st); });
-            Jnew = gradient(rv(slot), rg(slot), false);
-            ++ngrad;
-            info.step_kind = GANMRES_STEP_NGMRES;
-            info.n_beta = wk + 1;
-            for (int i = 0; i <= wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = beta[i];
+            for (int a = 0; a < K; ++a)
+                for (int bb = a; bb < K; ++bb) {
+                    run(KC_REDUCE, [&] { return launch_dot<T>(vecs[a], vecs[bb], d * N, partial, dres, st); });
+                    G[a * K + bb] = G[bb * K + a] = fetch();
+                }
         }
-        hist.push_back(slot);
-        while ((int)hist.size() > p.w + 1) hist.pop_front();
+        std::vector<double> beta = lsq_from_gram(K, G);
+        for (double x : beta)
+            if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
+        return beta;
+    }
+
+    void finish_step(const ganmres_solver_params& p, void* v, T* Vn, T* Gn, double Jnew,
+                     double Jq, double rho, int ngrad, ganmres_step_info& info) {
         ++k;
-        const double ginf = maxabs(rg(slot));
+        const double ginf = maxabs(Gn);
         Jcur = Jnew;
-        HIPCHK(hipMemcpyAsync(v, rv(slot), sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         info.k = k;
         info.J = Jnew;
@@ -898,6 +879,129 @@ class Problem : public ProblemBase {
         info.stop = (ginf <= p.eps_rel * g0inf) || (k >= p.n_iter);
         if (!std::isfinite(Jnew) || !std::isfinite(ginf))
             throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient");
+    }
+
+    void start(const ganmres_solver_params& p, void* v, T* V0, T* G0, int& ngrad) {
+        HIPCHK(hipMemcpyAsync(V0, v, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        Jcur = gradient(V0, G0, false);
+        ++ngrad;
+        g0inf = maxabs(G0);
+        if (!std::isfinite(Jcur) || !std::isfinite(g0inf))
+            throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient at v^0");
+        k = 0;
+        rho_bar = 1.0;
+        started = true;
+    }
+
+    void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) override {
+        ensure_solver(p.w, p.accel);
+        info = ganmres_step_info{};
+        if (p.accel == GANMRES_ACCEL_AA) step_aa(p, v, info);
+        else step_ngmres(p, v, info);
+    }
+
+    // One iteration of GA-NGMRES(w; sigma, tau) (Alg. 3).
+    void step_ngmres(const ganmres_solver_params& p, void* v, ganmres_step_info& info) {
+        int ngrad = 0;
+        if (!started) {
+            start(p, v, rv(0), rg(0), ngrad);
+            hist.assign(1, 0);
+        }
+        const int cur = hist.back();
+        double Jq = 0.0;
+        const double rho = line_search(rv(cur), rg(cur), p, info, Jq);
+        T* q = static_cast<T*>(qb->p);
+        T* gq = static_cast<T*>(gqb->p);
+        gradient(q, gq, true);
+        ++ngrad;
+        // the free slot (not in the window)
+        int slot = -1;
+        for (int i = 0; i < (int)ring_v.size(); ++i)
+            if (std::find(hist.begin(), hist.end(), i) == hist.end()) {
+                slot = i;
+                break;
+            }
+        double Jnew;
+        if (is_fp(k, p)) {
+            std::swap(ring_v[slot], qb);
+            std::swap(ring_g[slot], gqb);
+            Jnew = Jq;
+            info.step_kind = GANMRES_STEP_FP;
+        } else {
+            const int wk = std::min(k, p.w);
+            std::vector<const T*> vecs(wk + 2);
+            vecs[0] = gq;
+            for (int i = 0; i <= wk; ++i) vecs[i + 1] = rg(hist[hist.size() - 1 - i]);
+            const std::vector<double> beta = gram_lsq(vecs);
+            std::vector<const T*> xs(wk + 1);
+            for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
+            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), beta.data(), wk + 1, rv(slot), d * N, st); });
+            Jnew = gradient(rv(slot), rg(slot), false);
+            ++ngrad;
+            info.step_kind = GANMRES_STEP_NGMRES;
+            info.n_beta = wk + 1;
+            for (int i = 0; i <= wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = beta[i];
+        }
+        hist.push_back(slot);
+        while ((int)hist.size() > p.w + 1) hist.pop_front();
+        finish_step(p, v, rv(slot), rg(slot), Jnew, Jq, rho, ngrad, info);
+    }
+
+    // One iteration of GA-AA(w; sigma, tau): Alg. 2 with the alternation of
+    // Alg. 3.  Ring slots hold (r, q) = (v - q(v), q(v)); slots 0/1 of the
+    // (v, g) ring alternate as the current and the next iterate.
+    void step_aa(const ganmres_solver_params& p, void* v, ganmres_step_info& info) {
+        int ngrad = 0;
+        if (!started) {
+            start(p, v, rv(0), rg(0), ngrad);
+            aa_cur = 0;
+            hist.clear();
+        }
+        T* Vc = rv(aa_cur);
+        T* Gc = rg(aa_cur);
+        const int nxt = 1 - aa_cur;
+        double Jq = 0.0;
+        const double rho = line_search(Vc, Gc, p, info, Jq);
+        T* q = static_cast<T*>(qb->p);
+        const int wk = std::min(k, p.w);
+        // the free (r, q) slot
+        int slot = -1;
+        for (int i = 0; i < (int)aa_r.size(); ++i)
+            if (std::find(hist.begin(), hist.end(), i) == hist.end()) {
+                slot = i;
+                break;
+            }
+        if (slot >= 0) {
+            run(KC_VEC, [&] { return launch_axpy<T>(Vc, -1.0, q, ar(slot), d * N, st); });
+            HIPCHK(hipMemcpyAsync(aq(slot), q, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        }
+        double Jnew;
+        if (is_fp(k, p) || wk == 0) {
+            // v^{k+1} = q: the trial buffer becomes the next iterate, and its
+            // forward solve from the line search is reused
+            std::swap(ring_v[nxt], qb);
+            Jnew = gradient(rv(nxt), rg(nxt), true);
+            info.step_kind = GANMRES_STEP_FP;
+        } else {
+            std::vector<const T*> vecs(wk + 1);
+            vecs[0] = ar(slot);
+            for (int i = 1; i <= wk; ++i) vecs[i] = ar(hist[hist.size() - i]);
+            const std::vector<double> xi = gram_lsq(vecs);
+            std::vector<const T*> xs(wk);
+            for (int i = 1; i <= wk; ++i) xs[i - 1] = aq(hist[hist.size() - i]);
+            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), xi.data(), wk, rv(nxt), d * N, st); });
+            Jnew = gradient(rv(nxt), rg(nxt), false);
+            info.step_kind = GANMRES_STEP_AA;
+            info.n_beta = wk;
+            for (int i = 0; i < wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = xi[i];
+        }
+        ++ngrad;
+        if (slot >= 0) {
+            hist.push_back(slot);
+            while ((int)hist.size() > p.w) hist.pop_front();
+        }
+        aa_cur = nxt;
+        finish_step(p, v, rv(nxt), rg(nxt), Jnew, Jq, rho, ngrad, info);
     }
 };
 
@@ -1026,7 +1130,8 @@ int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info) {
     if (!h || !p || !v) return GANMRES_EINVAL;
     if (p->w < 0 || p->w > GANMRES_MAX_WINDOW || p->sigma < 0 || p->tau < 0 ||
-        (p->sigma + p->tau) == 0 || p->n_iter < 1 || p->max_backtracks < 0) {
+        (p->sigma + p->tau) == 0 || p->n_iter < 1 || p->max_backtracks < 0 ||
+        (p->accel != GANMRES_ACCEL_NGMRES && p->accel != GANMRES_ACCEL_AA)) {
         h->err = "invalid solver parameters";
         return GANMRES_EINVAL;
     }

@@ -174,3 +174,59 @@ def test_c0_trajectory_parity_f64():
         if info.stop:
             break
     assert info.k == res.iterations
+
+
+KIND = {0: "ngmres", 1: "fp", 2: "aa"}
+
+
+@pytest.mark.parametrize("variant", ["GA", "ALT"])
+def test_c0_ga_aa_trajectory_parity_f64(variant):
+    """GA-AA(5; 2, 1) (Alg. 2 with the alternation of Alg. 3) on the c0 recipe
+    against the oracle's loop: every iterate to 1e-8, J, the step kinds and the
+    line-search trial counts exactly, the mixing coefficients to 1e-6."""
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c0")
+    P = oracle_problem(wl)
+    sv = wl.solver
+    n_iter = 12
+    res = ong.solve(P, w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                    n_iter=n_iter, keep_iterates=True, accel="aa", variant=variant)
+    G = make_gpu(P, wl, torch.float64)
+    params = gan.SolveParams(w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                             n_iter=n_iter, accel=gan.ACCEL_AA,
+                             variant=gan.VARIANT_GA if variant == "GA" else gan.VARIANT_ALT)
+    v = G.new_velocity()
+    for k in range(1, n_iter + 1):
+        info = G.step(params, v)
+        rec = res.records[k - 1]
+        err = rel(host(v), res.iterates[k])
+        say(f"  k {k} {KIND[info.step_kind]} J {info.J:.12e} / {rec.J:.12e} "
+            f"iterate err {err:.2e} trials {info.n_trials}/{rec.trials}")
+        assert KIND[info.step_kind] == rec.kind
+        assert info.n_trials == rec.trials
+        assert err <= 1e-8
+        assert abs(info.J - rec.J) <= 1e-10 * abs(rec.J)
+        if rec.beta is not None:
+            assert info.n_beta == len(rec.beta)
+            np.testing.assert_allclose(np.array(info.beta[:info.n_beta]), rec.beta, rtol=1e-6,
+                                       atol=1e-9)
+        if info.stop:
+            break
+    assert info.k == res.iterations
+
+
+def test_accelerator_change_needs_reset():
+    """Switching between GA-NGMRES and GA-AA inside a solve is an error; after
+    a reset the other accelerator starts cleanly."""
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c0", shape=(32, 32))
+    P = oracle_problem(wl)
+    G = make_gpu(P, wl, torch.float64)
+    v = G.new_velocity()
+    G.step(gan.SolveParams(w=3, sigma=2, tau=1, n_iter=5), v)
+    with pytest.raises(gan.GanmresError):
+        G.step(gan.SolveParams(w=3, sigma=2, tau=1, n_iter=5, accel=gan.ACCEL_AA), v)
+    G.reset()
+    v.zero_()
+    info = G.step(gan.SolveParams(w=3, sigma=2, tau=1, n_iter=5, accel=gan.ACCEL_AA), v)
+    assert info.k == 1 and KIND[info.step_kind] == "fp"

@@ -1,8 +1,8 @@
 // Mixed-radix (8/4/2/3) Stockham autosort FFT on data resident in LDS.
 //
-// Layout: PC pencils of length L interleaved as buf[i * PC + p], so that the
-// threads of a wavefront that share a butterfly index j touch consecutive
-// words.  One pass of radix R turns the L/R length-R sub-transforms of the
+// Layout: PC pencils of length L interleaved as buf[lpad(i * PC + p)], so
+// that the threads of a wavefront that share a butterfly index j touch
+// consecutive words.  One pass of radix R turns the L/R length-R sub-transforms of the
 // current stage into sub-transforms of length Ns*R:
 //   inputs  a_r = in[j + r L/R]                      (r = 0..R-1)
 //   twiddle a_r *= W^(k r L/(Ns R)),  k = j mod Ns,  W = exp(dir 2 pi i / L)
@@ -15,6 +15,14 @@
 #include "common.hpp"
 
 namespace gan {
+
+// LDS slot of complex element c of a transform buffer: one pad element after
+// every 16.  Accesses that stride over the pencil-interleaved layout (the
+// transposes between row-major global data and the tile, the first Stockham
+// pass) then spread over the LDS banks instead of hitting one bank per
+// stride.  A buffer of n elements occupies lpad_size(n) slots.
+__host__ __device__ inline int lpad(int c) { return c + (c >> 4); }
+__host__ __device__ inline int lpad_size(int n) { return n + (n >> 4) + 1; }
 
 template <typename T, int R>
 __host__ __device__ inline void dft_small(C2<T>* a, int dir) {
@@ -73,7 +81,7 @@ __host__ __device__ inline void stockham_butterfly(const C2<T>* in, C2<T>* out, 
     const int k = j % Ns;
     C2<T> a[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r) a[r] = in[((j + r * nb) << pcshift) + p];
+    for (int r = 0; r < R; ++r) a[r] = in[lpad(((j + r * nb) << pcshift) + p)];
     if (Ns > 1) {
         const int step = L / (Ns * R);
 #pragma unroll
@@ -86,7 +94,7 @@ __host__ __device__ inline void stockham_butterfly(const C2<T>* in, C2<T>* out, 
     dft_small<T, R>(a, dir);
     const int base = (j / Ns) * Ns * R + k;
 #pragma unroll
-    for (int r = 0; r < R; ++r) out[((base + r * Ns) << pcshift) + p] = a[r];
+    for (int r = 0; r < R; ++r) out[lpad(((base + r * Ns) << pcshift) + p)] = a[r];
 }
 
 template <typename T>
@@ -100,7 +108,78 @@ __host__ __device__ inline void stockham_dispatch(int R, const C2<T>* in, C2<T>*
     }
 }
 
+// Radix plan of make_radices below as a compile-time value.
+struct RadixPlanCT {
+    int n;
+    int r[16];
+};
+constexpr RadixPlanCT radix_plan_ct(int L) {
+    RadixPlanCT P{0, {}};
+    int m = L, p2 = 0, p3 = 0;
+    while (m % 2 == 0) {
+        m /= 2;
+        ++p2;
+    }
+    while (m % 3 == 0) {
+        m /= 3;
+        ++p3;
+    }
+    while (p2 >= 3) {
+        P.r[P.n++] = 8;
+        p2 -= 3;
+    }
+    if (p2 == 2) P.r[P.n++] = 4;
+    if (p2 == 1) P.r[P.n++] = 2;
+    for (int i = 0; i < p3; ++i) P.r[P.n++] = 3;
+    return P;
+}
+
+// Stockham butterfly with the transform length L and the stage's sub-length
+// NS known at compile time: every division and modulus by them is constant.
+template <typename T, int R, int L, int NS>
+__device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t, int pcshift,
+                                             const C2<T>* tw, int dir) {
+    const int PC = 1 << pcshift;
+    const int p = t & (PC - 1);
+    const int j = t >> pcshift;
+    constexpr int nb = L / R;
+    const int k = j % NS;
+    C2<T> a[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[r] = in[lpad(((j + r * nb) << pcshift) + p)];
+    if constexpr (NS > 1) {
+        constexpr int step = L / (NS * R);
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+            C2<T> w = tw[k * r * step];
+            if (dir > 0) w.y = -w.y;
+            a[r] = cmul(a[r], w);
+        }
+    }
+    dft_small<T, R>(a, dir);
+    const int base = (j / NS) * NS * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) out[lpad(((base + r * NS) << pcshift) + p)] = a[r];
+}
+
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+// block_fft for a compile-time length L (NT threads per block): the radix
+// sequence, the stage lengths and the twiddle strides are constants.
+template <typename T, int L, int NT, int S = 0, int NS = 1>
+__device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int pcshift, int dir) {
+    constexpr RadixPlanCT P = radix_plan_ct(L);
+    if constexpr (S == P.n) {
+        return a;
+    } else {
+        constexpr int R = P.r[S];
+        const int nbt = (L / R) << pcshift;
+        for (int t = threadIdx.x; t < nbt; t += NT)
+            stockham_butterfly_ct<T, R, L, NS>(a, b, t, pcshift, tw, dir);
+        __syncthreads();
+        return block_fft_ct<T, L, NT, S + 1, NS * R>(b, a, tw, pcshift, dir);
+    }
+}
+
 // Whole transform of the PC pencils held in LDS buffer a (b is scratch of the
 // same size).  Returns the buffer holding the result.  Ends with a barrier.
 // tw: the twiddle table (typically a copy in LDS); the plan's radices stay in

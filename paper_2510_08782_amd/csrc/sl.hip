@@ -9,13 +9,18 @@
 // FP32 whatever the grid index.
 //
 // LDS-tiled gather.  A block owns a tile of output points (3-D: 32 x 8 x TZ,
-// 2-D: 64 x 32) and stages the source field over the tile plus a halo of
-// H+1 cells below and H+2 above every axis.  Every tap then comes from LDS at
-// a compile-time offset from one base address per point.  The caller passes
-// an upper bound on the displacement (cells); the launcher picks the smallest
-// halo variant that covers it, and a launch whose bound exceeds its halo takes
-// the direct global gather instead.  Both paths give the same values: only
-// where the taps are read from changes.
+// 2-D: 64 x 32).  Before the gather it reduces, over the tile, the smallest
+// and largest floor of the departure displacement along every axis, and
+// stages the source region those departure points can touch: along each
+// axis the tile shifted by the smallest floor, widened by the spread of the
+// floors plus the 3 extra nodes of the cubic stencil.  The region's capacity
+// is fixed per variant (spread up to S cells per axis); every tap then comes
+// from LDS at a compile-time offset from one base address per point.  Only
+// the spread of the displacements within a tile must fit, not their size, so
+// long but smooth displacements (large line-search trials) stay on the LDS
+// path.  A tile whose spread exceeds S reads its taps directly from global
+// memory instead.  Both paths give the same values: only where the taps are
+// read from changes.
 #include <cmath>
 
 #include "launch.hpp"
@@ -59,7 +64,28 @@ __device__ inline void axis_taps(int i, T disp, int n, int stride, int* off, T* 
     off[3] = b2 * stride;
 }
 
-// Direct (L1/L2) gather of one field at point (i0,i1,i2) + (d0,d1,d2).
+// The 4 x taps of one row, weighted.  When the stencil does not wrap the taps
+// are consecutive elements and move with one 16-byte load per 4 bytes of
+// element width (global loads need only element alignment on this target);
+// wrapped stencils read them one by one.
+template <typename T>
+struct Quad {
+    T v[4];
+};
+template <typename T>
+__device__ inline T row_taps(const T* __restrict__ row, const int* o, bool contig, const T* w) {
+    if (contig) {
+        Quad<T> q;
+        __builtin_memcpy(&q, row + o[0], sizeof(q));
+        return w[0] * q.v[0] + w[1] * q.v[1] + w[2] * q.v[2] + w[3] * q.v[3];
+    }
+    return w[0] * row[o[0]] + w[1] * row[o[1]] + w[2] * row[o[2]] + w[3] * row[o[3]];
+}
+
+// Direct (L1/L2) gather of one field at point (i0,i1,i2) + (d0,d1,d2).  Used
+// by tiles whose departure points spread too far for the staged window, e.g.
+// the first line-search trials from v = 0, so it is written for scattered
+// access: 16 row loads per point instead of 64 element loads.
 template <typename T, int DIM>
 __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i0, int i1, int i2,
                                   T d0, T d1, T d2) {
@@ -67,6 +93,7 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
     T w1[4], w2[4];
     axis_taps(i1, d1, dm.n[1], dm.n[2], o1, w1);
     axis_taps(i2, d2, dm.n[2], 1, o2, w2);
+    const bool contig = o2[3] == o2[0] + 3;
     T acc = T(0);
     if constexpr (DIM == 3) {
         int o0[4];
@@ -76,54 +103,51 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
         for (int a = 0; a < 4; ++a) {
             T sa = T(0);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const T* row = s + o0[a] + o1[b];
-                sa += w1[b] * (w2[0] * row[o2[0]] + w2[1] * row[o2[1]] + w2[2] * row[o2[2]] +
-                               w2[3] * row[o2[3]]);
-            }
+            for (int b = 0; b < 4; ++b) sa += w1[b] * row_taps(s + o0[a] + o1[b], o2, contig, w2);
             acc += w0[a] * sa;
         }
     } else {
         // 2-D: axis 0 indexes independent slices
         const T* sl = s + (long long)i0 * dm.n[1] * dm.n[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const T* row = sl + o1[b];
-            acc += w1[b] * (w2[0] * row[o2[0]] + w2[1] * row[o2[1]] + w2[2] * row[o2[2]] +
-                            w2[3] * row[o2[3]]);
-        }
+        for (int b = 0; b < 4; ++b) acc += w1[b] * row_taps(sl + o1[b], o2, contig, w2);
     }
     return acc;
 }
 
 // ---- tile geometry -----------------------------------------------------------
 // 3-D: threads (32 x 8), each owns TZ points along z.  2-D: threads (64 x 4),
-// each owns 8 points along y (tile 64 x 32).  H is the halo: the staged region
-// covers departure displacements of up to H cells.
-template <typename T_, int DIM_, int H>
+// each owns 8 points along y (tile 64 x 32).  S is the capacity of the staged
+// region: up to S cells of spread of the displacement floors per axis.
+template <typename T_, int DIM_, int S_>
 struct Tile;
-template <typename T_, int H>
-struct Tile<T_, 3, H> {
+template <typename T_, int S_>
+struct Tile<T_, 3, S_> {
     using T = T_;
     static constexpr int DIM = 3;
     static constexpr int TX = 32, TY = 8, TZ = sizeof(T) == 4 ? 8 : 4;
-    static constexpr int HALO = H;
-    static constexpr int RX = TX + 2 * H + 3, RY = TY + 2 * H + 3, RZ = TZ + 2 * H + 3;
+    static constexpr int S = S_;
+    static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = TZ + S + 3;
+    // LDS row pitch: the two rows a wavefront reads (lanes 0-31 and 32-63)
+    // start half the banks apart
+    static constexpr int PX = 48;
+    static_assert(RX <= PX, "window wider than the row pitch");
     static constexpr int PTS = TZ;  // points per thread
 };
-template <typename T_, int H>
-struct Tile<T_, 2, H> {
+template <typename T_, int S_>
+struct Tile<T_, 2, S_> {
     using T = T_;
     static constexpr int DIM = 2;
     static constexpr int TX = 64, TY = 32, TZ = 1;
-    static constexpr int HALO = H;
-    static constexpr int RX = TX + 2 * H + 3, RY = TY + 2 * H + 3, RZ = 1;
+    static constexpr int S = S_;
+    static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = 1;
+    static constexpr int PX = RX;  // a wavefront reads one row
     static constexpr int PTS = 8;
 };
 
 template <class C>
 constexpr size_t tile_lds_bytes() {
-    return sizeof(typename C::T) * C::RX * C::RY * C::RZ;
+    return sizeof(typename C::T) * C::PX * C::RY * C::RZ;
 }
 
 // g mod n in [0, n): the common in-range case costs one compare.
@@ -131,38 +155,103 @@ __device__ inline int wrapn(int g, int n) {
     return (static_cast<unsigned>(g) < static_cast<unsigned>(n)) ? g : pmod(g, n);
 }
 
-// Stage src over the block's tile + halo (origin x0,y0,z0 of the tile).
+// The staged region of a tile: along axis a (0: x, 1: y, 2: z) it starts at
+// tile origin + lo[a] - 1 and spans ext[a] = T_a + spread_a + 3 nodes.
+struct Window {
+    int lo[3];
+    int ext[3];
+    bool lds;  // every spread fits the variant's capacity
+};
+
+__device__ inline int wave_min_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = min(x, __shfl_xor(x, o, 64));
+    return x;
+}
+__device__ inline int wave_max_i(int x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x = max(x, __shfl_xor(x, o, 64));
+    return x;
+}
+
+// Floor of a displacement as used for the window; the taps of the LDS path
+// use the unclamped floor, which agrees whenever the window is taken (all
+// floors of the tile within +-2^20).
+template <typename T>
+__device__ inline int disp_floor(T d) {
+    return static_cast<int>(floor(clamp_disp(d)));
+}
+
+// Block-wide window from per-thread floor ranges fmn/fmx (x, y, z order).
+// red: 6 ints per wave of LDS.  Contains a barrier.
+template <class C>
+__device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], int* red) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int m = wave_min_i(fmn[a]);
+        const int M = wave_max_i(fmx[a]);
+        if (lane == 0) {
+            red[wave * 6 + a] = m;
+            red[wave * 6 + 3 + a] = M;
+        }
+    }
+    __syncthreads();
+    Window w;
+    const int T3[3] = {C::TX, C::TY, C::TZ};
+    w.lds = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int m = red[a], M = red[3 + a];
+#pragma unroll
+        for (int q = 1; q < kThreads / 64; ++q) {
+            m = min(m, red[q * 6 + a]);
+            M = max(M, red[q * 6 + 3 + a]);
+        }
+        if (a == 2 && C::DIM == 2) m = M = 0;  // slice axis: no interpolation
+        const int spread = M - m;
+        w.lds = w.lds && spread <= C::S && m >= -(1 << 20) && M <= (1 << 20);
+        w.lo[a] = m;
+        w.ext[a] = (a == 2 && C::DIM == 2) ? 1 : T3[a] + spread + 3;
+    }
+    return w;
+}
+
+// Stage src over the window of the tile with origin (x0, y0, z0).
 // Global-to-LDS loads (global_load_lds_dword): a wavefront walks the rows of
 // the region and moves each row with one instruction per 64 dwords, lane l
 // writing dword l of the row; the wrapped x index of every lane is computed
 // once.  All of a wave's row loads are in flight together and no VGPRs hold
-// the data.  FP64 rows move as pairs of dwords.  Ends with a barrier.
+// the data.  FP64 rows move as pairs of dwords.  The LDS layout keeps the
+// variant's full row pitch PX and plane pitch RY.  Ends with a barrier.
 template <class C>
 __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ src,
-                             typename C::T* lds, int x0, int y0, int z0) {
+                             typename C::T* lds, int x0, int y0, int z0, const Window& w) {
     using T = typename C::T;
     constexpr int W = sizeof(T) / 4;                  // dwords per element
-    constexpr int ROWS = C::RY * C::RZ;
     constexpr int NW = kThreads / 64;
     constexpr int XP = (W * C::RX + 63) / 64;         // dword passes per row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int ex = w.ext[0], ey = w.ext[1], rows = w.ext[1] * w.ext[2];
+    const int ox = x0 + w.lo[0] - 1, oy = y0 + w.lo[1] - 1;
+    const int oz = C::DIM == 3 ? z0 + w.lo[2] - 1 : z0;
     int goff[XP];                                    // dword offset of the lane's element in a row
     bool xin[XP];
 #pragma unroll
     for (int u = 0; u < XP; ++u) {
         const int d = lane + 64 * u;
-        xin[u] = d < W * C::RX;
-        goff[u] = W * wrapn(x0 - C::HALO - 1 + d / W, dm.n[2]) + d % W;
+        xin[u] = d < W * ex;
+        goff[u] = W * wrapn(ox + d / W, dm.n[2]) + d % W;
     }
-    for (int r = wave; r < ROWS; r += NW) {
-        const int ry = r % C::RY, rz = r / C::RY;
-        const int gy = wrapn(y0 - C::HALO - 1 + ry, dm.n[1]);
+    for (int r = wave; r < rows; r += NW) {
+        const int ry = r % ey, rz = r / ey;
+        const int gy = wrapn(oy + ry, dm.n[1]);
         // 2-D: axis 0 indexes independent slices (no interpolation across it)
-        const int gz = C::DIM == 3 ? wrapn(z0 - C::HALO - 1 + rz, dm.n[0]) : z0;
+        const int gz = C::DIM == 3 ? wrapn(oz + rz, dm.n[0]) : z0;
         // N < 2^31 elements
         const unsigned* row = reinterpret_cast<const unsigned*>(src + (gz * dm.n[1] + gy) * dm.n[2]);
-        unsigned* dst = reinterpret_cast<unsigned*>(lds + r * C::RX);
+        unsigned* dst = reinterpret_cast<unsigned*>(lds + (rz * C::RY + ry) * C::PX);
 #pragma unroll
         for (int u = 0; u < XP; ++u)
             if (xin[u]) __builtin_amdgcn_global_load_lds(row + goff[u], dst + 64 * u, 4, 0, 0);
@@ -172,64 +261,46 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
 }
 
 // Tap base and weights along one axis for the LDS path: local index of the
-// node f-1 (relative to the region origin) for point index li within the tile.
-template <typename T, int HALO, int R>
-__device__ inline int lds_axis(int li, T disp, T* w) {
+// node f-1 for point index li within the tile, the window starting at
+// floor minimum lo (minus one).
+template <typename T, int R>
+__device__ inline int lds_axis(int li, T disp, int lo, T* w) {
     const T fl = floor(disp);
     lagrange4(disp - fl, w);
-    int l = li + static_cast<int>(fl) + HALO;  // = (li + fl + HALO + 1) - 1
+    int l = li + static_cast<int>(fl) - lo;
     l = l < 0 ? 0 : (l > R - 4 ? R - 4 : l);
     return l;
 }
 
-// Interpolate from the staged region at tile-local point (lx,ly,lz) displaced by d.
+// Interpolate from the staged window at tile-local point (lx,ly,lz) displaced by d.
 template <class C>
-__device__ inline typename C::T gather_lds(const typename C::T* lds, int lx, int ly, int lz,
-                                           typename C::T d0, typename C::T d1, typename C::T d2) {
+__device__ inline typename C::T gather_lds(const typename C::T* lds, const Window& win, int lx,
+                                           int ly, int lz, typename C::T d0, typename C::T d1,
+                                           typename C::T d2) {
     using T = typename C::T;
     T wx[4], wy[4];
-    const int bx = lds_axis<T, C::HALO, C::RX>(lx, d2, wx);
-    const int by = lds_axis<T, C::HALO, C::RY>(ly, d1, wy);
+    const int bx = lds_axis<T, C::RX>(lx, d2, win.lo[0], wx);
+    const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], wy);
     T acc = T(0);
     if constexpr (C::DIM == 3) {
         T wz[4];
-        const int bz = lds_axis<T, C::HALO, C::RZ>(lz, d0, wz);
-        const T* base = lds + (bz * C::RY + by) * C::RX + bx;
-#ifdef GAN_SL_PRELOAD
-        T val[64];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-            for (int b = 0; b < 4; ++b)
-#pragma unroll
-                for (int c = 0; c < 4; ++c) val[(a * 4 + b) * 4 + c] = base[(a * C::RY + b) * C::RX + c];
+        const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], wz);
+        const T* base = lds + (bz * C::RY + by) * C::PX + bx;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             T sa = T(0);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const T* row = val + (a * 4 + b) * 4;
+                const T* row = base + (a * C::RY + b) * C::PX;
                 sa += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
             }
             acc += wz[a] * sa;
         }
-#else
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            T sa = T(0);
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const T* row = base + (a * C::RY + b) * C::RX;
-                sa += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
-            }
-            acc += wz[a] * sa;
-        }
-#endif
     } else {
-        const T* base = lds + by * C::RX + bx;
+        const T* base = lds + by * C::PX + bx;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const T* row = base + b * C::RX;
+            const T* row = base + b * C::PX;
             acc += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
         }
     }
@@ -287,26 +358,40 @@ int tile_blocks(const Dims& dm) {
 }
 
 // ---- semi-Lagrangian step --------------------------------------------------------
-// EPI 0: out = I[src];  1: out = fac * I[src];
-// EPI 2 (source factor, src = delta): out = 1 + sgn h/2 (I[d] + d) + h^2/2 d I[d]
-// `bound` >= max |disp| (cells); beyond the halo the direct gather is used.
-template <class C, int EPI>
+template <typename T, int EPI>
+__device__ inline T step_epilogue(T r, const T* __restrict__ src, const T* __restrict__ fac,
+                                  long long lin, T ht, T sgn) {
+    if constexpr (EPI == 1) r *= fac[lin];
+    if constexpr (EPI == 2) {
+        const T dc = src[lin];
+        r = T(1) + sgn * T(0.5) * ht * (r + dc) + T(0.5) * ht * ht * dc * r;
+    }
+    return r;
+}
+
+// LDS = true: tiles whose window fits (the others return at once);
+// LDS = false: the remaining tiles, every tap read from global memory.  Two
+// kernels, so that the LDS path does not carry the direct gather's registers;
+// the second is launched only when the displacement bound allows a tile to
+// exceed the window.
+template <class C, int EPI, bool LDS>
 __global__ void __launch_bounds__(kThreads) sl_step_kernel(
     Dims dm, const typename C::T* __restrict__ src, const typename C::T* __restrict__ disp,
-    const typename C::T* __restrict__ fac, typename C::T ht, typename C::T sgn, int bound,
+    const typename C::T* __restrict__ fac, typename C::T ht, typename C::T sgn,
     typename C::T* __restrict__ out) {
     using T = typename C::T;
     constexpr int DIM = C::DIM;
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
+    __shared__ int red[6 * (kThreads / 64)];
     const PointMap<C> pm(dm);
     if (!pm.valid) return;
-    const bool use_lds = bound <= C::HALO;
     const long long N = dm.N;
-    // displacements of the thread's points, loaded before the staging
+    // displacements of the thread's points and their floor ranges
     T d0[C::PTS], d1[C::PTS], d2[C::PTS];
     long long lin[C::PTS];
     bool in[C::PTS];
+    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         int lx, ly, lz;
@@ -324,52 +409,83 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
                 d1[k] = disp[lin[k]];
                 d2[k] = disp[N + lin[k]];
             }
+            const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                fmn[q] = min(fmn[q], f[q]);
+                fmx[q] = max(fmx[q], f[q]);
+            }
         }
     }
-    if (use_lds) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0);
+    const Window win = tile_window<C>(fmn, fmx, red);
+    if (win.lds != LDS) return;
+    if constexpr (LDS) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         if (!in[k]) continue;
         int lx, ly, lz;
         pm.local(k, lx, ly, lz);
         T r;
-        if (use_lds) {
-            r = gather_lds<C>(lds, lx, ly, lz, d0[k], d1[k], d2[k]);
-        } else {
+        if constexpr (LDS)
+            r = gather_lds<C>(lds, win, lx, ly, lz, d0[k], d1[k], d2[k]);
+        else
             r = gather_global<T, DIM>(dm, src, pm.z0 + lz, pm.y0 + ly, pm.x0 + lx, d0[k], d1[k],
                                       d2[k]);
-        }
-        if constexpr (EPI == 1) r *= fac[lin[k]];
-        if constexpr (EPI == 2) {
-            const T dc = src[lin[k]];
-            r = T(1) + sgn * T(0.5) * ht * (r + dc) + T(0.5) * ht * ht * dc * r;
-        }
-        out[lin[k]] = r;
+        out[lin[k]] = step_epilogue<T, EPI>(r, src, fac, lin[k], ht, sgn);
     }
 }
 
 // ---- characteristics -------------------------------------------------------------
 // dX = -(u + I[u](i - u)) / 2 (state, +v) and dY = (u + I[u](i + u)) / 2
-// (adjoint, -v), u_c = s_c v_c.  Component c of v is staged in LDS in turn;
-// the predictor points only depend on u at the grid point.  ubound >= max |u|.
-template <class C, bool DOX, bool DOY>
+// (adjoint, -v), u_c = s_c v_c.  The predictor points only depend on u at the
+// grid point, so the window is known before any staging; component c of v is
+// then staged in LDS in turn.  With both directions the window covers both
+// sets of predictor points.
+template <class C, bool DOX, bool DOY, bool LDS>
 __global__ void __launch_bounds__(kThreads) characteristics_kernel(
     Dims dm, const typename C::T* __restrict__ v, typename C::T s0, typename C::T s1,
-    typename C::T s2, int ubound, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
+    typename C::T s2, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
     using T = typename C::T;
     constexpr int DIM = C::DIM;
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
+    __shared__ int red[6 * (kThreads / 64)];
     const PointMap<C> pm(dm);
     if (!pm.valid) return;
-    const bool use_lds = ubound <= C::HALO;
     const long long N = dm.N;
     const T s[3] = {s0, s1, s2};
+    // floor ranges of the predictor displacements -u (state) / +u (adjoint)
+    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+    for (int k = 0; k < C::PTS; ++k) {
+        int lx, ly, lz;
+        pm.local(k, lx, ly, lz);
+        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
+        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const T e = v[c * N + lin] * s[c];
+            const int q = DIM - 1 - c;  // axis slot: x, y, z
+            if (DOX) {
+                const int f = disp_floor(-e);
+                fmn[q] = min(fmn[q], f);
+                fmx[q] = max(fmx[q], f);
+            }
+            if (DOY) {
+                const int f = disp_floor(e);
+                fmn[q] = min(fmn[q], f);
+                fmx[q] = max(fmx[q], f);
+            }
+        }
+    }
+    const Window win = tile_window<C>(fmn, fmx, red);
+    if (win.lds != LDS) return;
     for (int c = 0; c < DIM; ++c) {
         const T* vc = v + c * N;
-        if (use_lds) {
-            __syncthreads();
-            stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0);
+        if constexpr (LDS) {
+            if (c > 0) __syncthreads();
+            stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0, win);
         }
 #pragma unroll 1
         for (int k = 0; k < C::PTS; ++k) {
@@ -391,13 +507,13 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
                 e2 = u[1];
             }
             if (DOX) {
-                const T iv = use_lds ? gather_lds<C>(lds, lx, ly, lz, -e0, -e1, -e2)
-                                     : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
+                const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, -e0, -e1, -e2)
+                                 : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
                 dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * iv);
             }
             if (DOY) {
-                const T iv = use_lds ? gather_lds<C>(lds, lx, ly, lz, e0, e1, e2)
-                                     : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
+                const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, e0, e1, e2)
+                                 : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
                 dY[c * N + lin] = T(0.5) * (u[c] + s[c] * iv);
             }
         }
@@ -423,28 +539,35 @@ __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restr
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// Variant choice: the smallest halo that covers the bound; beyond the
-// largest the widest variant runs its direct-gather path.
+// Variant choice from a bound b on |displacement| (cells): the floors then lie
+// in [-b, b], so a tile's spread is at most 2b, and the smallest capacity
+// covering 2b is taken; beyond the largest, the largest runs and only tiles
+// whose own spread exceeds it gather from global memory.
 template <typename T, int DIM>
-int pick_halo(int bound) {
-    if (DIM == 2) return bound <= 4 ? 4 : 8;
-    if (sizeof(T) == 8) return bound <= 1 ? 1 : 2;
-    return bound <= 1 ? 1 : (bound <= 2 ? 2 : 4);
+int pick_capacity(int bound) {
+    const long long sp = 2LL * bound;
+    if (DIM == 2) return sp <= 8 ? 8 : 16;
+    if (sizeof(T) == 8) return sp <= 2 ? 2 : 4;
+    return sp <= 2 ? 2 : (sp <= 4 ? 4 : 8);
 }
 
 template <class C, bool DOX, bool DOY>
 void char_launch(const Dims& dm, const typename C::T* v, const double* s, int ubound,
                  typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
-    characteristics_kernel<C, DOX, DOY><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-        dm, v, T(s[0]), T(s[1]), T(C::DIM == 3 ? s[2] : 0.0), ubound, dX, dY);
+    const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
+    characteristics_kernel<C, DOX, DOY, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+        dm, v, T(s[0]), T(s[1]), s2, dX, dY);
+    if (2LL * ubound > C::S)
+        characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
+            dm, v, T(s[0]), T(s[1]), s2, dX, dY);
 }
 
 template <class C>
 void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubound,
                typename C::T* dX, typename C::T* dY, hipStream_t st) {
     // 3-D: one launch per direction (each keeps one gather in flight per
-    // thread); 2-D: both directions in one launch
+    // thread and a window of its own); 2-D: both directions in one launch
     if (C::DIM == 3 || !(dX && dY)) {
         if (dX) char_launch<C, true, false>(dm, v, s, ubound, dX, dY, st);
         if (dY) char_launch<C, false, true>(dm, v, s, ubound, dX, dY, st);
@@ -453,37 +576,43 @@ void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubou
     }
 }
 
+template <class C, int EPI>
+void step_kernels(const Dims& dm, const typename C::T* src, const typename C::T* disp,
+                  const typename C::T* fac, double ht, double sgn, int bound,
+                  typename C::T* out, hipStream_t st) {
+    using T = typename C::T;
+    sl_step_kernel<C, EPI, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
+        dm, src, disp, fac, T(ht), T(sgn), out);
+    if (2LL * bound > C::S)
+        sl_step_kernel<C, EPI, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
+            dm, src, disp, fac, T(ht), T(sgn), out);
+}
+
 template <class C>
 void step_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
                  const typename C::T* fac, int bound, typename C::T* out, hipStream_t st) {
-    using T = typename C::T;
-    if (fac)
-        sl_step_kernel<C, 1><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-            dm, src, disp, fac, T(0), T(0), bound, out);
-    else
-        sl_step_kernel<C, 0><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-            dm, src, disp, fac, T(0), T(0), bound, out);
+    if (fac) step_kernels<C, 1>(dm, src, disp, fac, 0.0, 0.0, bound, out, st);
+    else step_kernels<C, 0>(dm, src, disp, fac, 0.0, 0.0, bound, out, st);
 }
 
 template <class C>
 void factor_launch(const Dims& dm, const typename C::T* delta, const typename C::T* disp,
                    double ht, double sgn, int bound, typename C::T* out, hipStream_t st) {
-    using T = typename C::T;
-    sl_step_kernel<C, 2><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-        dm, delta, disp, nullptr, T(ht), T(sgn), bound, out);
+    step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, bound, out, st);
 }
 
 // Calls f(Tile<...>{}) with the variant chosen for `bound`.
 template <typename T, typename F>
 void dispatch_tile(const Dims& dm, int bound, F&& f) {
     if (dm.dim == 3) {
-        const int h = pick_halo<T, 3>(bound);
-        if (h == 1) f(Tile<T, 3, 1>{});
-        else if (h == 2 || sizeof(T) == 8) f(Tile<T, 3, 2>{});
-        else f(Tile<T, 3, 4>{});
+        const int c = pick_capacity<T, 3>(bound);
+        if (c == 2) f(Tile<T, 3, 2>{});
+        else if constexpr (sizeof(T) == 8) f(Tile<T, 3, 4>{});
+        else if (c == 4) f(Tile<T, 3, 4>{});
+        else f(Tile<T, 3, 8>{});
     } else {
-        if (pick_halo<T, 2>(bound) == 4) f(Tile<T, 2, 4>{});
-        else f(Tile<T, 2, 8>{});
+        if (pick_capacity<T, 2>(bound) == 8) f(Tile<T, 2, 8>{});
+        else f(Tile<T, 2, 16>{});
     }
 }
 

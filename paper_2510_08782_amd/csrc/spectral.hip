@@ -14,6 +14,8 @@
 // kernel exploits: one LDS pass per axis and time point, no full 3-D FFT.
 // Full transforms (half spectrum (n0, n1, n2/2+1)) serve the regulariser,
 // its inverse and the Leray projection.
+#include <type_traits>
+
 #include "fft_core.hpp"
 #include "launch.hpp"
 #include "reduce.hpp"
@@ -33,10 +35,14 @@ constexpr int kLdsBudget = 64 * 1024;
 // log2 of the complex pencils per tile for kernels whose tile holds 2 PC real
 // pencils of length L (2 PC L <= kFftThreads * kItems), with two complex LDS
 // buffers and the twiddle table within the LDS budget.
+// Two padded buffers of PC L complex elements and the twiddle table.
+size_t fft_lds_bytes(int PC, int L, int bytes_per_complex) {
+    return (size_t)(2 * lpad_size(PC * L) + L) * bytes_per_complex;
+}
 int pc_shift_real(int L, int bytes_per_complex, long long npencils) {
     int s = 0;
     while ((2 << (s + 1)) * L <= kFftThreads * kItems && (2LL << s) < npencils &&
-           (2 * (1 << (s + 1)) + 1) * L * bytes_per_complex <= kLdsBudget && s < 5)
+           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= kLdsBudget && s < 5)
         ++s;
     return s;
 }
@@ -44,12 +50,9 @@ int pc_shift_real(int L, int bytes_per_complex, long long npencils) {
 int pc_shift_cplx(int L, int bytes_per_complex, long long npencils) {
     int s = 0;
     while ((1 << (s + 1)) * L <= kFftThreads * kItems && (1LL << s) < npencils &&
-           (2 * (1 << (s + 1)) + 1) * L * bytes_per_complex <= kLdsBudget && s < 5)
+           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= kLdsBudget && s < 5)
         ++s;
     return s;
-}
-size_t fft_lds_bytes(int PC, int L, int bytes_per_complex) {
-    return (size_t)(2 * PC + 1) * L * bytes_per_complex;
 }
 
 // Pencils along `axis` of an (n0, n1, w) array (w = n2 for real data, n2/2+1
@@ -72,6 +75,34 @@ template <typename T>
 __device__ inline C2<T>* twiddles_to_lds(const FftPlan<T>& pl, C2<T>* tws) {
     for (int m = threadIdx.x; m < pl.L; m += kFftThreads) tws[m] = pl.tw[m];
     return tws;
+}
+
+// Transform of the tile: compiled for length LC when LC > 0, else driven by
+// the runtime plan.
+template <typename T, int LC>
+__device__ inline C2<T>* tile_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, const C2<T>* tw,
+                                  int pcshift, int dir) {
+    if constexpr (LC > 0)
+        return block_fft_ct<T, LC, kFftThreads>(a, b, tw, pcshift, dir);
+    else
+        return block_fft<T>(a, b, pl, tw, pcshift, dir);
+}
+
+// Lengths with compiled transforms (the grid sizes of the workloads); any
+// other 2^a 3^b length takes the runtime plan.
+template <typename F>
+void with_length(int L, F&& f) {
+    switch (L) {
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        case 96: f(std::integral_constant<int, 96>{}); break;
+        case 128: f(std::integral_constant<int, 128>{}); break;
+        case 192: f(std::integral_constant<int, 192>{}); break;
+        case 256: f(std::integral_constant<int, 256>{}); break;
+        case 384: f(std::integral_constant<int, 384>{}); break;
+        case 512: f(std::integral_constant<int, 512>{}); break;
+        default: f(std::integral_constant<int, 0>{}); break;
+    }
 }
 
 // Item e of a tile of NP real pencils x L: its pencil r and position i.
@@ -104,15 +135,15 @@ struct DerivArgs {
 // out = [out +] sum_t w_t G_t d/dx_axis F_t over one tile of 2 PC real pencils.
 // The loads of G_t and F_{t+1} are issued before the transforms of step t so
 // that they complete while the LDS passes run.
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a) {
-    const int L = a.pl.L;
+    const int L = LC > 0 ? LC : a.pl.L;
     const int PC = 1 << a.pcshift;
     const int npshift = a.pcshift + 1;
     C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + PC * L;
+    C2<T>* bufB = bufA + lpad_size(PC * L);
     const FftPlan<T>& pl = a.pl;
-    const C2<T>* tw = twiddles_to_lds(a.pl, bufB + PC * L);
+    const C2<T>* tw = twiddles_to_lds(a.pl, bufB + lpad_size(PC * L));
     const Dims& dm = a.dm;
     const long long npen = pencil_count(dm, a.axis, dm.n[2]);
     const long long stride = pencil_stride(dm, a.axis, dm.n[2]);
@@ -133,7 +164,7 @@ __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a)
         if (q < nitems) {
             int r, i;
             item_pos(a.axis, q, L, npshift, r, i);
-            slot[e] = 2 * ((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
+            slot[e] = 2 * lpad((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
             ok[e] = p0 + r < npen;
             if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
         }
@@ -155,13 +186,13 @@ __global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a)
             if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
             if (more) fv[e] = ok[e] ? Fn[off[e]] : T(0);
         }
-        C2<T>* X = block_fft<T>(bufA, bufB, pl, tw, a.pcshift, -1);
+        C2<T>* X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
         for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
             const int i = q >> a.pcshift;
-            X[q] = cmuli(X[q], T(wavenumber_odd(i, L)) * inv_l);
+            X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
         }
         __syncthreads();
-        const C2<T>* Y = block_fft<T>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
+        const C2<T>* Y = tile_fft<T, LC>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
         const T* yflat = reinterpret_cast<const T*>(Y);
         const T wt = T(a.w[t]);
 #pragma unroll
@@ -190,16 +221,16 @@ struct OutPtrs {
 
 // Real rows (axis 2) of type TI -> half-spectrum rows computed and stored in
 // precision TC, for field blockIdx.y.
-template <typename TI, typename TC>
+template <typename TI, typename TC, int LC>
 __global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<TC> pl0, int pcshift,
                                                                InPtrs<TI> ip, SpecPtrs<TC> sp) {
     using T = TC;
-    const int L = pl0.L;
+    const int L = LC > 0 ? LC : pl0.L;
     const int PC = 1 << pcshift;
     C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + PC * L;
+    C2<T>* bufB = bufA + lpad_size(PC * L);
     const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
     const TI* in = ip.in[blockIdx.y];
     C2<T>* spec = sp.spec[blockIdx.y];
     const long long rows = (long long)dm.n[0] * dm.n[1];
@@ -218,19 +249,19 @@ __global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<
         const int q = threadIdx.x + e * kFftThreads;
         if (q < nitems) {
             const int r = q / L, i = q - r * L;
-            flat[2 * ((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+            flat[2 * lpad((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
         }
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, -1);
+    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
     const int nh = dm.n2h;
     for (int q = threadIdx.x; q < 2 * PC * nh; q += kFftThreads) {
         const int r = q / nh, k = q - r * nh;
         if (q0 + r >= rows) continue;
         const int p = r & (PC - 1);
-        const C2<T> zk = Z[(k << pcshift) + p];
+        const C2<T> zk = Z[lpad((k << pcshift) + p)];
         const int km = k == 0 ? 0 : L - k;
-        const C2<T> zm = Z[(km << pcshift) + p];
+        const C2<T> zm = Z[lpad((km << pcshift) + p)];
         C2<T> o;
         if ((r >> pcshift) == 0) o = cmk(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
         else o = cmk(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
@@ -240,16 +271,16 @@ __global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<
 
 // In-place complex transform of the half spectrum along axis 0 or 1, on tiles
 // of PC adjacent pencils.
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<T> pl0, int axis,
                                                                int pcshift, int dir,
                                                                SpecPtrs<T> sp) {
-    const int L = pl0.L;
+    const int L = LC > 0 ? LC : pl0.L;
     const int PC = 1 << pcshift;
     C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + PC * L;
+    C2<T>* bufB = bufA + lpad_size(PC * L);
     const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
     C2<T>* spec = sp.spec[blockIdx.y];
     const int nh = dm.n2h;
     const long long npen = pencil_count(dm, axis, nh);
@@ -269,28 +300,28 @@ __global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<
 #pragma unroll
     for (int e = 0; e < kItems; ++e) {
         const int q = threadIdx.x + e * kFftThreads;
-        if (q < nitems) bufA[q] = vals[e];
+        if (q < nitems) bufA[lpad(q)] = vals[e];
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, dir);
+    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
 #pragma unroll
     for (int e = 0; e < kItems; ++e) {
         const int q = threadIdx.x + e * kFftThreads;
-        if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[q];
+        if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
     }
 }
 
 // Half-spectrum rows -> real rows: out = scale * x [+ add].
-template <typename T>
+template <typename T, int LC>
 __global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<T> pl0, int pcshift,
                                                                T scale, SpecPtrs<T> sp,
                                                                OutPtrs<T> op) {
-    const int L = pl0.L;
+    const int L = LC > 0 ? LC : pl0.L;
     const int PC = 1 << pcshift;
     C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + PC * L;
+    C2<T>* bufB = bufA + lpad_size(PC * L);
     const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + PC * L);
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
     const C2<T>* spec = sp.spec[blockIdx.y];
     T* out = op.out[blockIdx.y];
     const T* add = op.add[blockIdx.y];
@@ -324,10 +355,10 @@ __global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<
             a.y = -a.y;
             b.y = -b.y;
         }
-        bufA[(i << pcshift) + p] = cmk(a.x - b.y, a.y + b.x);
+        bufA[lpad((i << pcshift) + p)] = cmk(a.x - b.y, a.y + b.x);
     }
     __syncthreads();
-    const C2<T>* Z = block_fft<T>(bufA, bufB, pl, tw, pcshift, +1);
+    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
     T addv[kItems];
 #pragma unroll
     for (int e = 0; e < kItems; ++e) {
@@ -340,7 +371,7 @@ __global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<
         const int q = threadIdx.x + e * kFftThreads;
         const int r = q / L, i = q - r * L;
         if (q >= 2 * nitems || q0 + r >= rows) continue;
-        const C2<T> z = Z[(i << pcshift) + (r & (PC - 1))];
+        const C2<T> z = Z[lpad((i << pcshift) + (r & (PC - 1)))];
         out[(q0 + r) * L + i] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e];
     }
 }
@@ -537,7 +568,10 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     }
     const int PC = 1 << a.pcshift;
     const long long tiles = (npen + 2 * PC - 1) / (2 * PC);
-    deriv_axis_kernel<T><<<(unsigned)tiles, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(a);
+    with_length(L, [&](auto lc) {
+        deriv_axis_kernel<T, decltype(lc)::value>
+            <<<(unsigned)tiles, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(a);
+    });
     return hipGetLastError();
 }
 
@@ -557,8 +591,10 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const int sh = pc_shift_real(L, (int)sizeof(C2<TC>), rows);
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
-        r2c_rows_kernel<TI, TC><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(
-            dm, pl.p[2], sh, ip, sp);
+        with_length(L, [&](auto lc) {
+            r2c_rows_kernel<TI, TC, decltype(lc)::value>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[2], sh, ip, sp);
+        });
     }
     for (int axis = 1; axis >= 3 - dm.dim; --axis) {
         const int L = dm.n[axis];
@@ -566,8 +602,11 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen);
         const int PC = 1 << sh;
         dim3 g((unsigned)((npen + PC - 1) / PC), count);
-        c2c_axis_kernel<TC><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(
-            dm, pl.p[axis], axis, sh, -1, sp);
+        with_length(L, [&](auto lc) {
+            c2c_axis_kernel<TC, decltype(lc)::value>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[axis], axis,
+                                                                               sh, -1, sp);
+        });
     }
     return hipGetLastError();
 }
@@ -590,8 +629,11 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
         const int PC = 1 << sh;
         dim3 g((unsigned)((npen + PC - 1) / PC), count);
-        c2c_axis_kernel<T><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
-            dm, pl.p[axis], axis, sh, +1, sp);
+        with_length(L, [&](auto lc) {
+            c2c_axis_kernel<T, decltype(lc)::value>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(dm, pl.p[axis], axis,
+                                                                              sh, +1, sp);
+        });
     }
     {
         const int L = dm.n[2];
@@ -599,8 +641,11 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const int sh = pc_shift_real(L, (int)sizeof(C2<T>), rows);
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
-        c2r_rows_kernel<T><<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
-            dm, pl.p[2], sh, T(scale), sp, op);
+        with_length(L, [&](auto lc) {
+            c2r_rows_kernel<T, decltype(lc)::value>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(dm, pl.p[2], sh,
+                                                                              T(scale), sp, op);
+        });
     }
     return hipGetLastError();
 }

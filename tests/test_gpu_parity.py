@@ -116,6 +116,31 @@ def test_edge_cases_f64(edge):
     G.close()
 
 
+# Long, smooth displacements: tiles whose displacement floors spread less than
+# the staged window's capacity take the LDS path with a shifted window, the
+# others gather from global memory; both within one launch.
+LARGE = [
+    ("shift3d_x3", "c2", (24, 32, 64), 2, 3.0),
+    ("far3d_x8", "c3", (16, 24, 32), 1, 8.0),
+    ("far2d_x20", "c0", (48, 64), 2, 20.0),
+]
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("edge", LARGE, ids=[e[0] for e in LARGE])
+def test_large_displacement_parity(edge, prec):
+    ename, name, shape, nt, vscale = edge
+    say(f"large {ename} shape {shape} nt {nt} vscale {vscale} {prec}")
+    wl = synth.workload(name, shape=shape)
+    wl.vstar = wl.vstar * vscale
+    P = as_precision(oracle_problem(wl, nt=nt), prec)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    G = make_gpu(P, wl, dtype)
+    for pname, v in probes(wl).items():
+        check_probe(P, G, round_to(v, prec), dtype, TOL[prec], pname)
+    G.close()
+
+
 def test_gradient_is_deterministic():
     wl = synth.workload("c2", shape=(24, 32, 48))
     P = oracle_problem(wl, nt=2)

@@ -816,11 +816,20 @@ class Problem : public ProblemBase {
         int trials = 0;
         bool accepted = false;
         for (int t = 0; t <= p.max_backtracks; ++t) {
-            run(KC_VEC, [&] { return launch_axpy<T>(Vc, rho, s, q, d * N, st); });
             Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
-            Jq = objective_trial(q, Rq, um0 + rho * smax);
+            const double bound = Jcur + p.c_armijo * rho * gs;
             ++trials;
-            if (Jq < Jcur + p.c_armijo * rho * gs) {
+            // J(q) = mismatch + alpha/2 R(q) with mismatch >= 0: a trial whose
+            // regulariser term alone reaches the Armijo bound fails whatever
+            // its transport gives (the same expression as in finish_J, so the
+            // decision is the one the full evaluation would take)
+            if (0.5 * cfg.alpha * Rq >= bound) {
+                rho *= 0.5;
+                continue;
+            }
+            run(KC_VEC, [&] { return launch_axpy<T>(Vc, rho, s, q, d * N, st); });
+            Jq = objective_trial(q, Rq, um0 + rho * smax);
+            if (Jq < bound) {
                 rho_bar = (t == 0) ? 2.0 * rho : rho;
                 if (p.rho_cap > 0.0) rho_bar = std::min(rho_bar, p.rho_cap);
                 accepted = true;

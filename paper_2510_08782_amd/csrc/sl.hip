@@ -119,13 +119,13 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
 // 3-D: threads (32 x 8), each owns TZ points along z.  2-D: threads (64 x 4),
 // each owns 8 points along y (tile 64 x 32).  S is the capacity of the staged
 // region: up to S cells of spread of the displacement floors per axis.
-template <typename T_, int DIM_, int S_>
+template <typename T_, int DIM_, int S_, int TZ_ = (sizeof(T_) == 4 ? 8 : 4)>
 struct Tile;
-template <typename T_, int S_>
-struct Tile<T_, 3, S_> {
+template <typename T_, int S_, int TZ_>
+struct Tile<T_, 3, S_, TZ_> {
     using T = T_;
     static constexpr int DIM = 3;
-    static constexpr int TX = 32, TY = 8, TZ = sizeof(T) == 4 ? 8 : 4;
+    static constexpr int TX = 32, TY = 8, TZ = TZ_;
     static constexpr int S = S_;
     static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = TZ + S + 3;
     // LDS row pitch: the two rows a wavefront reads (lanes 0-31 and 32-63)
@@ -134,8 +134,8 @@ struct Tile<T_, 3, S_> {
     static_assert(RX <= PX, "window wider than the row pitch");
     static constexpr int PTS = TZ;  // points per thread
 };
-template <typename T_, int S_>
-struct Tile<T_, 2, S_> {
+template <typename T_, int S_, int TZ_>
+struct Tile<T_, 2, S_, TZ_> {
     using T = T_;
     static constexpr int DIM = 2;
     static constexpr int TX = 64, TY = 32, TZ = 1;
@@ -224,7 +224,7 @@ __device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], i
 // once.  All of a wave's row loads are in flight together and no VGPRs hold
 // the data.  FP64 rows move as pairs of dwords.  The LDS layout keeps the
 // variant's full row pitch PX and plane pitch RY.  Ends with a barrier.
-template <class C>
+template <class C, bool WAIT = true>
 __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ src,
                              typename C::T* lds, int x0, int y0, int z0, const Window& w) {
     using T = typename C::T;
@@ -256,8 +256,10 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
         for (int u = 0; u < XP; ++u)
             if (xin[u]) __builtin_amdgcn_global_load_lds(row + goff[u], dst + 64 * u, 4, 0, 0);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __syncthreads();
+    if constexpr (WAIT) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
 }
 
 // Tap base and weights along one axis for the LDS path: local index of the
@@ -272,39 +274,67 @@ __device__ inline int lds_axis(int li, T disp, int lo, T* w) {
     return l;
 }
 
-// Interpolate from the staged window at tile-local point (lx,ly,lz) displaced by d.
+// Stencil of one departure point in the staged window: offset of its first
+// tap and the cubic weights per axis.
+template <typename T>
+struct Stencil {
+    int base;
+    T wx[4], wy[4], wz[4];
+};
+
 template <class C>
-__device__ inline typename C::T gather_lds(const typename C::T* lds, const Window& win, int lx,
-                                           int ly, int lz, typename C::T d0, typename C::T d1,
-                                           typename C::T d2) {
+__device__ inline Stencil<typename C::T> lds_stencil(const Window& win, int lx, int ly, int lz,
+                                                     typename C::T d0, typename C::T d1,
+                                                     typename C::T d2) {
     using T = typename C::T;
-    T wx[4], wy[4];
-    const int bx = lds_axis<T, C::RX>(lx, d2, win.lo[0], wx);
-    const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], wy);
+    Stencil<T> st;
+    const int bx = lds_axis<T, C::RX>(lx, d2, win.lo[0], st.wx);
+    const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], st.wy);
+    if constexpr (C::DIM == 3) {
+        const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], st.wz);
+        st.base = (bz * C::RY + by) * C::PX + bx;
+    } else {
+        st.base = by * C::PX + bx;
+    }
+    return st;
+}
+
+// Tensor-product cubic interpolation of a staged field at a stencil.
+template <class C>
+__device__ inline typename C::T lds_interp(const typename C::T* lds,
+                                           const Stencil<typename C::T>& st) {
+    using T = typename C::T;
+    const T* base = lds + st.base;
     T acc = T(0);
     if constexpr (C::DIM == 3) {
-        T wz[4];
-        const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], wz);
-        const T* base = lds + (bz * C::RY + by) * C::PX + bx;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             T sa = T(0);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
                 const T* row = base + (a * C::RY + b) * C::PX;
-                sa += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+                sa += st.wy[b] *
+                      (st.wx[0] * row[0] + st.wx[1] * row[1] + st.wx[2] * row[2] + st.wx[3] * row[3]);
             }
-            acc += wz[a] * sa;
+            acc += st.wz[a] * sa;
         }
     } else {
-        const T* base = lds + by * C::PX + bx;
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const T* row = base + b * C::PX;
-            acc += wy[b] * (wx[0] * row[0] + wx[1] * row[1] + wx[2] * row[2] + wx[3] * row[3]);
+            acc += st.wy[b] *
+                   (st.wx[0] * row[0] + st.wx[1] * row[1] + st.wx[2] * row[2] + st.wx[3] * row[3]);
         }
     }
     return acc;
+}
+
+// Interpolate from the staged window at tile-local point (lx,ly,lz) displaced by d.
+template <class C>
+__device__ inline typename C::T gather_lds(const typename C::T* lds, const Window& win, int lx,
+                                           int ly, int lz, typename C::T d0, typename C::T d1,
+                                           typename C::T d2) {
+    return lds_interp<C>(lds, lds_stencil<C>(win, lx, ly, lz, d0, d1, d2));
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
@@ -520,6 +550,85 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
     }
 }
 
+// Characteristics with every component of v staged at once (DIM windows in
+// LDS): the stencil of a predictor point (weights, first tap) is computed
+// once and serves all DIM components, and with both directions one staging
+// serves X and Y.  Tiles that do not fit are left to
+// characteristics_kernel<C, DOX, DOY, false>.
+template <class C, bool DOX, bool DOY>
+__global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
+    Dims dm, const typename C::T* __restrict__ v, typename C::T s0, typename C::T s1,
+    typename C::T s2, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
+    using T = typename C::T;
+    constexpr int DIM = C::DIM;
+    constexpr int PLANE = C::PX * C::RY * C::RZ;  // elements per staged component
+    extern __shared__ double2 sl_smem[];
+    T* lds = reinterpret_cast<T*>(sl_smem);
+    __shared__ int red[6 * (kThreads / 64)];
+    const PointMap<C> pm(dm);
+    if (!pm.valid) return;
+    const long long N = dm.N;
+    const T s[3] = {s0, s1, s2};
+    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+    for (int k = 0; k < C::PTS; ++k) {
+        int lx, ly, lz;
+        pm.local(k, lx, ly, lz);
+        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
+        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const T e = v[c * N + lin] * s[c];
+            const int q = DIM - 1 - c;
+            if (DOX) {
+                const int f = disp_floor(-e);
+                fmn[q] = min(fmn[q], f);
+                fmx[q] = max(fmx[q], f);
+            }
+            if (DOY) {
+                const int f = disp_floor(e);
+                fmn[q] = min(fmn[q], f);
+                fmx[q] = max(fmx[q], f);
+            }
+        }
+    }
+    const Window win = tile_window<C>(fmn, fmx, red);
+    if (!win.lds) return;
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        if (c + 1 < DIM)
+            stage<C, false>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
+        else
+            stage<C, true>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
+    }
+#pragma unroll 1
+    for (int k = 0; k < C::PTS; ++k) {
+        int lx, ly, lz;
+        pm.local(k, lx, ly, lz);
+        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
+        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+        T u[3];
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) u[q] = v[q * N + lin] * s[q];
+        const T e0 = DIM == 3 ? u[0] : T(0), e1 = DIM == 3 ? u[1] : u[0];
+        const T e2 = DIM == 3 ? u[2] : u[1];
+        if (DOX) {
+            const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, -e0, -e1, -e2);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
+        }
+        if (DOY) {
+            const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, e0, e1, e2);
+#pragma unroll
+            for (int c = 0; c < DIM; ++c)
+                dY[c * N + lin] = T(0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
+        }
+    }
+}
+
 // max_c max_i |s_c v_c(i)| (NaN/inf counted as 1e30): FP64 block partials
 template <typename T>
 __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restrict__ v,
@@ -563,11 +672,38 @@ void char_launch(const Dims& dm, const typename C::T* v, const double* s, int ub
             dm, v, T(s[0]), T(s[1]), s2, dX, dY);
 }
 
+template <class C, bool DOX, bool DOY>
+void char_all_launch(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+                     typename C::T* dX, typename C::T* dY, hipStream_t st) {
+    using T = typename C::T;
+    const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
+    characteristics_all_kernel<C, DOX, DOY>
+        <<<tile_blocks<C>(dm), kThreads, C::DIM * tile_lds_bytes<C>(), st>>>(dm, v, T(s[0]), T(s[1]),
+                                                                          s2, dX, dY);
+    if (2LL * ubound > C::S)
+        characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
+            dm, v, T(s[0]), T(s[1]), s2, dX, dY);
+}
+
+// LDS per workgroup on gfx950
+constexpr size_t kMaxLds = 160 * 1024;
+
 template <class C>
 void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubound,
                typename C::T* dX, typename C::T* dY, hipStream_t st) {
-    // 3-D: one launch per direction (each keeps one gather in flight per
-    // thread and a window of its own); 2-D: both directions in one launch
+    using T = typename C::T;
+    // both directions: all components staged at once (one staging and one
+    // stencil per point serve X and Y), on 3-D tiles of 4 planes, where that
+    // fits; a single direction stages one component at a time, which keeps
+    // more workgroups per CU
+    using CA = Tile<T, C::DIM, C::S, 4>;
+    if constexpr (C::DIM * tile_lds_bytes<CA>() <= kMaxLds / 2) {
+        if (dX && dY) {
+            char_all_launch<CA, true, true>(dm, v, s, ubound, dX, dY, st);
+            return;
+        }
+    }
+    // one component staged at a time, one launch per direction in 3-D
     if (C::DIM == 3 || !(dX && dY)) {
         if (dX) char_launch<C, true, false>(dm, v, s, ubound, dX, dY, st);
         if (dY) char_launch<C, false, true>(dm, v, s, ubound, dX, dY, st);

@@ -193,6 +193,57 @@ def c3_throughput(torch, gan, synth):
     return out
 
 
+def c4_throughput(torch, gan, synth):
+    """The batched 2-D set: 16 problems each at 96^2, 192^2 and 384^2 (FP32,
+    H1, nt=4, alpha per problem), one batch handle per size; 15 GA-NGMRES
+    iterations of every problem from v = 0.  Aggregate gradient evaluations
+    per second over the whole set."""
+    import numpy as np
+    wls = synth.batch_workloads()
+    sv = wls[0].solver
+    params = gan.SolveParams(w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
+                             n_iter=sv["n_iter"])
+    groups = {}
+    for w in wls:
+        groups.setdefault(w.shape, []).append(w)
+    batches = []
+    for shape, ws in groups.items():
+        dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+        m0 = dev(np.stack([w.m0 for w in ws]))
+        vstar = dev(np.stack([w.vstar for w in ws], axis=1))
+        alphas = [w.alpha for w in ws]
+        gen = gan.BatchProblem(m0, m0, ws[0].nt, alphas, ws[0].reg_order)
+        gen.eval_objective(vstar)
+        m1 = gen.get_field("state", ws[0].nt)
+        gen.close()
+        batches.append((shape, gan.BatchProblem(m0, m1, ws[0].nt, alphas, ws[0].reg_order)))
+    # warm-up: one iteration per batch
+    for _, B in batches:
+        B.step(params, B.new_velocity())
+        B.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ngrad = 0
+    per = {}
+    for shape, B in batches:
+        t1 = time.perf_counter()
+        v = B.new_velocity()
+        for _ in range(params.n_iter):
+            infos = B.step(params, v)
+            ngrad += sum(i.n_grad for i in infos)
+        torch.cuda.synchronize()
+        per[f"{shape[0]}x{shape[1]}"] = {"problems": B.count,
+                                         "seconds": round(time.perf_counter() - t1, 4),
+                                         "rel_grad_max": max(i.ginf / i.g0inf for i in infos)}
+        B.reset()
+    dt = time.perf_counter() - t0
+    ngrad += len(wls)  # g(v^0) of every problem
+    for _, B in batches:
+        B.close()
+    return {"problems": len(wls), "iterations_each": params.n_iter, "seconds": round(dt, 4),
+            "grad_evals": ngrad, "grad_evals_per_s": round(ngrad / dt, 1), "per_size": per}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -202,6 +253,7 @@ def main():
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-c3", action="store_true", help="skip the 256^3 throughput figures")
+    ap.add_argument("--no-c4", action="store_true", help="skip the batched 2-D set")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -285,6 +337,10 @@ def main():
     if not args.no_c3:
         log("256^3 throughput (c3)")
         extra["c3_256cubed"] = c3_throughput(torch, gan, synth)
+
+    if not args.no_c4:
+        log("batched 2-D set (c4)")
+        extra["c4_batched_2d"] = c4_throughput(torch, gan, synth)
 
     cpu = None
     if not args.no_cpu:

@@ -114,6 +114,31 @@ typedef struct {
 int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1,
                    void* stream, ganmres_handle** out);
 
+/* A batch: count (1..64) independent 2-D problems of the same shape and
+ * model in one handle, stacked along a leading axis, so that every kernel
+ * launch serves all of them (the small-image regime, where one problem cannot
+ * fill the GPU).  cfg describes one problem (dim must be 2 when count > 1);
+ * alpha: host array of count regularisation weights (NULL: cfg->alpha for
+ * all).  m0, m1: device images of shape (count, n[0], n[1]).  On a batch
+ * handle a velocity has shape (2, count, n[0], n[1]) (component-major: all
+ * problems' first components, then all second components); the evaluation
+ * calls return sums over the problems (ganmres_batch_values gives them one
+ * by one), and ganmres_step advances every problem by one iteration, each with
+ * its own line search, window and mixing coefficients.  The problems share the
+ * iteration counter k, so the GA switch of Alg. 3 is common; a problem whose
+ * stopping rule holds keeps iterating until the caller stops.  A single
+ * handle is the batch of one.  Errors: as ganmres_create, and GANMRES_EINVAL
+ * for count outside [1, 64], count > 1 with dim 3, or alpha[i] <= 0. */
+int ganmres_create_batch(const ganmres_config* cfg, int count, const double* alpha,
+                         const void* m0, const void* m1, void* stream, ganmres_handle** out);
+
+/* Number of problems in the handle (1 for ganmres_create; 0 for NULL). */
+int ganmres_batch_count(const ganmres_handle* h);
+
+/* Per-problem J and 1/2 ||m(1) - m1||_h^2 of the last objective or gradient
+ * evaluation (host arrays of ganmres_batch_count entries, either nullable). */
+int ganmres_batch_values(ganmres_handle* h, double* J, double* mismatch);
+
 /* Release the handle and its workspace (NULL is accepted). */
 int ganmres_destroy(ganmres_handle* h);
 
@@ -153,7 +178,8 @@ int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs)
  * velocity, in: v^k, out: v^{k+1}.  On the first call after create or reset, v
  * is v^0 and g(v^0) is evaluated first.  The handle keeps k, the stored step
  * rho, the window (the last w+1 pairs (v, g), or the last w pairs
- * (v - q(v), q(v)) for AA) and ||g(v^0)||_inf.  info: host, nullable.
+ * (v - q(v), q(v)) for AA) and ||g(v^0)||_inf.  info: host array of
+ * ganmres_batch_count(h) entries (one per problem), nullable.
  * Errors: GANMRES_EINVAL (w < 0 or > GANMRES_MAX_WINDOW, sigma = tau = 0,
  * negative counts, unknown accel, accel or w changed without a reset),
  * GANMRES_ELINESEARCH, GANMRES_ELSQ, GANMRES_ENONFINITE. */

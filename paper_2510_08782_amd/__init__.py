@@ -75,6 +75,10 @@ def lib():
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     L.ganmres_create.argtypes = [ctypes.POINTER(Config), vp, vp, vp, ctypes.POINTER(vp)]
+    L.ganmres_create_batch.argtypes = [ctypes.POINTER(Config), ip, dp, vp, vp, vp,
+                                       ctypes.POINTER(vp)]
+    L.ganmres_batch_count.argtypes = [vp]
+    L.ganmres_batch_values.argtypes = [vp, dp, dp]
     L.ganmres_destroy.argtypes = [vp]
     L.ganmres_last_error.argtypes = [vp]
     L.ganmres_last_error.restype = ctypes.c_char_p
@@ -237,6 +241,13 @@ class Problem:
             out[lib().ganmres_kernel_name(kidx).decode()] = (ms.value, cnt.value)
         return out
 
+    def values(self):
+        """Per-problem J and mismatch of the last evaluation (lists)."""
+        n = lib().ganmres_batch_count(self.h)
+        J, mis = (ctypes.c_double * n)(), (ctypes.c_double * n)()
+        self._check(lib().ganmres_batch_values(self.h, J, mis))
+        return list(J), list(mis)
+
     def solve(self, params: SolveParams, v0=None, callback=None):
         """Run GA-NGMRES, or GA-AA when params.accel is ACCEL_AA, from v0
         (default 0) until the stopping rule holds."""
@@ -281,3 +292,50 @@ def transport_objective():
             return (grad_out.to(g.dtype) * cell) * g, None
 
     return TransportObjective
+
+
+class BatchProblem(Problem):
+    """count same-size 2-D problems stacked along a leading axis in one handle
+    (one launch per kernel serves all of them).  m0, m1: device images of
+    shape (count, n0, n1); alphas: one regularisation weight per problem.
+    Velocities are component-major, shape (2, count, n0, n1); step() returns
+    one StepInfo per problem, and the evaluation calls return sums over the
+    problems (values() gives them one by one)."""
+
+    def __init__(self, m0, m1, nt, alphas, reg_order, model="advection", stream=None):
+        import torch
+        if not m0.is_cuda or m0.dim() != 3:
+            raise ValueError("m0/m1 must be device tensors of shape (count, n0, n1)")
+        if m0.dtype not in (torch.float32, torch.float64) or m1.dtype != m0.dtype:
+            raise ValueError("m0/m1 must share dtype float32 or float64")
+        self.torch = torch
+        self.dtype = m0.dtype
+        self.m0 = m0.contiguous()
+        self.m1 = m1.contiguous()
+        self.count = int(m0.shape[0])
+        alphas = [float(a) for a in alphas]
+        if len(alphas) != self.count:
+            raise ValueError("one alpha per problem")
+        self.shape = tuple(m0.shape)
+        self.dim = 2
+        cfg = Config(2, (ctypes.c_int * 3)(int(m0.shape[1]), int(m0.shape[2]), 1), int(nt),
+                     ADVECTION if model == "advection" else CONTINUITY, 0, int(reg_order),
+                     alphas[0], F32 if m0.dtype == torch.float32 else F64, 1)
+        self.cfg = cfg
+        self.nt = int(nt)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(m0.device)
+        h = ctypes.c_void_p()
+        al = (ctypes.c_double * self.count)(*alphas)
+        rc = lib().ganmres_create_batch(ctypes.byref(cfg), self.count, al, self.m0.data_ptr(),
+                                        self.m1.data_ptr(),
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise GanmresError(rc, lib().ganmres_last_error(None).decode())
+        self.h = h
+
+    def step(self, params: SolveParams, v):
+        infos = (StepInfo * self.count)()
+        cp = params.to_c()
+        self._check(lib().ganmres_step(self.h, ctypes.byref(cp), self._vec(v).data_ptr(), infos))
+        return list(infos)
+

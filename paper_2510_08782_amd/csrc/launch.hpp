@@ -31,30 +31,48 @@ hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, d
                                 double sgn, int bound, T* out, hipStream_t st);
 
 // ---- reductions and vector kernels (vec.hip) -------------------------------
-// Deterministic two-stage FP64 reductions; the result lands in res[0] (device).
+// Arrays are segmented: a batch of nseg independent problems stacked along the
+// slowest grid axis.  Element (c, s, i) of an array sits at
+// c * cstride + s * seglen + i: component c < ncomp, segment s < nseg,
+// i < seglen.  A single problem is one segment.
+constexpr int kMaxSeg = 64;
+struct Seg {
+    int nseg;
+    int ncomp;
+    long long seglen;
+    long long cstride;
+};
+struct SegCoef {
+    double c[kMaxSeg];
+};
+
+// Deterministic two-stage FP64 reductions; segment s's result lands in res[s]
+// (device).
 int reduction_blocks(long long n);
 // sum (a - b)^2 ; if lam != nullptr also writes lam = b - a
 template <typename T>
-hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, long long n, double* partial,
+hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, const Seg& g, double* partial,
                              double* res, hipStream_t st);
 template <typename T>
-hipError_t launch_dot(const T* a, const T* b, long long n, double* partial, double* res,
+hipError_t launch_dot(const T* a, const T* b, const Seg& g, double* partial, double* res,
                       hipStream_t st);
 // max |a| with NaN mapped to +inf
 template <typename T>
-hipError_t launch_maxabs(const T* a, long long n, double* partial, double* res, hipStream_t st);
-// Gram matrix of K <= 8 vectors: res holds the K(K+1)/2 upper-triangle entries
-// (a, b >= a) in row order
+hipError_t launch_maxabs(const T* a, const Seg& g, double* partial, double* res, hipStream_t st);
+// Gram matrix of K <= 8 vectors per segment: res[q nseg + s] holds packed
+// upper-triangle entry q (pairs (a, b >= a) in row order) of segment s
 template <typename T>
-hipError_t launch_gram(const T* const* vecs, int K, long long n, double* partial, double* res,
+hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partial, double* res,
                        hipStream_t st);
-// out = a + s b
+// out = a + s[seg] b   (s: host array, one coefficient per segment)
 template <typename T>
-hipError_t launch_axpy(const T* a, double s, const T* b, T* out, long long n, hipStream_t st);
-// out = q + sum_i c[i] (q - x[i])   (K <= 65; the NGMRES update)
+hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Seg& g,
+                       hipStream_t st);
+// out = q + sum_k coef[k nseg + s] (q - x[k]) on segment s   (K <= 65; the
+// NGMRES / AA update; coef: device table)
 template <typename T>
-hipError_t launch_combine(const T* q, const T* const* x, const double* c, int K, T* out,
-                          long long n, hipStream_t st);
+hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int K, T* out,
+                          const Seg& g, hipStream_t st);
 
 // ---- spectral kernels (spectral.hip) ----------------------------------------
 template <typename T>
@@ -85,6 +103,7 @@ struct SpecOpParams {
     int p;             // regulariser order
     double alpha;
     int leray;         // apply the Leray projection
+    const double* alpha_seg;  // device, one alpha per stacked 2-D problem (nullable)
 };
 // gh[c] = alpha l_p vh[c] + P bh[c]   (bh may alias gh; vh is an FP64 spectrum)
 template <typename T>
@@ -95,15 +114,17 @@ hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<doubl
 template <typename T>
 hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
                                C2<T>* const* sh, C2<T>* const* keep, hipStream_t st);
-// res[0] = sum w l_p Re(vh conj sh), res[1] = sum w l_p |sh|^2 (full-spectrum sums)
+// Per stacked problem s (one for 3-D): res[s] = sum w l_p Re(vh conj sh),
+// res[nseg + s] = sum w l_p |sh|^2 (full-spectrum sums)
 template <typename T>
 hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
                              C2<T>* const* sh, double* partial, double* res, hipStream_t st);
-// vh[c] += rho sh[c]
+// vh[c] += rho[s] sh[c] on stacked problem s (rho: host array)
 template <typename T>
-hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, double rho,
+hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, const double* rho,
                             C2<T>* const* sh, hipStream_t st);
-// res[0] = sum_c sum_k l_p(k) |vh_c(k)|^2 over the full spectrum (half-spectrum weights)
+// res[s] = sum_c sum_k l_p(k) |vh_c(k)|^2 over the full spectrum of stacked
+// problem s (half-spectrum weights)
 template <typename T>
 hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* const* vh,
                                 double* partial, double* res, hipStream_t st);

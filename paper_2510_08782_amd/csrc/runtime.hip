@@ -190,7 +190,10 @@ class ProblemBase {
     virtual double objective(const void* v, bool keep, double* mismatch) = 0;
     virtual double gradient(const void* v, void* g, bool reuse) = 0;
     virtual double precond(const void* g, void* s) = 0;
-    virtual void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) = 0;
+    // info: one entry per stacked problem
+    virtual void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) = 0;
+    virtual int count() const = 0;
+    virtual void values(double* J, double* mismatch) const = 0;
     virtual void reset() = 0;
     virtual void get_field(int which, int j, void* out) = 0;
     virtual long long workspace_bytes() const = 0;
@@ -234,19 +237,32 @@ class Problem : public ProblemBase {
     CT* wh[3];
     CT* sk[3];                   // spectrum of the last search direction (line search)
     const void* vh_of = nullptr;  // velocity whose spectrum vh holds
-    bool reg_from_device = true;  // R(v) of the next finish_J comes from the device sum
+    bool reg_from_device = true;  // R(v) of the next finish_J comes from the device sums
     double *partial, *dres;
+    // stacked independent 2-D problems (1 for a single problem): per-problem
+    // points, regularisation weights and scalars
+    int nb = 1;
+    long long Nt = 0;
+    std::vector<double> alpha_s;
+    double* alpha_dev = nullptr;
+    double* coef_dev = nullptr;    // combine coefficients, K x nb
+    std::vector<double> reg_s;     // R(v) per problem of the last evaluation
+    std::vector<double> J_s, mis_s;
     // displacement bounds of the velocity whose departure points are current
     double umax = 0.0;              // >= max |u| (cells per step)
     int ubound = 0, dbound = 0;     // ceil bounds for the predictor and for X / Y
     const void* umax_of = nullptr;  // velocity umax belongs to
-    double* hres;  // pinned host results
+    double* hres = nullptr;  // pinned host results
+    double* hup = nullptr;   // pinned staging of host -> device tables
+    // slots of the device / host result buffers (per-problem values from s)
+    static constexpr int kRes = 8192;
+    static constexpr int R_MIS = 0, R_REG = 256, R_DOT = 512, R_SMAX = 768, R_CROSS = 1024,
+                         R_MAX = 1280, R_UMAX = 1536, R_GRAM = 2048;
     long long ws_bytes = 0;
     bool fwd_valid = false;
     const void* fwd_v = nullptr;
     bool adj_valid = false;
     bool y_valid = false;
-    double reg_cached = 0.0;
 
     // solver
     int wcap = -1;
@@ -258,7 +274,7 @@ class Problem : public ProblemBase {
     std::deque<int> hist;
     bool started = false;
     int k = 0;
-    double rho_bar = 1.0, g0inf = 0.0, Jcur = 0.0;
+    std::vector<double> rho_bar, g0inf, Jcur;  // per problem
 
     // timing events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
@@ -278,11 +294,15 @@ class Problem : public ProblemBase {
         return static_cast<CT*>(bufs.back()->p);
     }
 
-    Problem(const ganmres_config& c, const void* m0_in, const void* m1_in, hipStream_t s)
+    // count > 1 (2-D only): count problems of shape n stacked along axis 0,
+    // with regularisation weights alpha_in[0..count) (nullptr: cfg.alpha)
+    Problem(const ganmres_config& c, const void* m0_in, const void* m1_in, hipStream_t s,
+            int count = 1, const double* alpha_in = nullptr)
         : cfg(c), st(s) {
         d = c.dim;
+        nb = count;
         dm.dim = d;
-        dm.n[0] = d == 3 ? c.n[0] : 1;
+        dm.n[0] = d == 3 ? c.n[0] : count;
         dm.n[1] = d == 3 ? c.n[1] : c.n[0];
         dm.n[2] = d == 3 ? c.n[2] : c.n[1];
         dm.N = (long long)dm.n[0] * dm.n[1] * dm.n[2];
@@ -290,6 +310,16 @@ class Problem : public ProblemBase {
         dm.NH = (long long)dm.n[0] * dm.n[1] * dm.n2h;
         N = dm.N;
         NH = dm.NH;
+        Nt = N / nb;
+        alpha_s.assign(nb, c.alpha);
+        if (alpha_in)
+            for (int i = 0; i < nb; ++i) alpha_s[i] = alpha_in[i];
+        reg_s.assign(nb, 0.0);
+        J_s.assign(nb, 0.0);
+        mis_s.assign(nb, 0.0);
+        rho_bar.assign(nb, 1.0);
+        g0inf.assign(nb, 0.0);
+        Jcur.assign(nb, 0.0);
         cell = 1.0;
         for (int a = 0; a < 3; ++a) {
             h[a] = 2.0 * M_PI / dm.n[a];
@@ -366,11 +396,20 @@ class Problem : public ProblemBase {
             bufs.back()->alloc(sizeof(double) * 64 * 1024);
             partial = static_cast<double*>(bufs.back()->p);
             bufs.emplace_back(new DevBuf);
-            bufs.back()->alloc(sizeof(double) * 128);
+            bufs.back()->alloc(sizeof(double) * kRes);
             dres = static_cast<double*>(bufs.back()->p);
-
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(double) * kMaxSeg);
+            alpha_dev = static_cast<double*>(bufs.back()->p);
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(double) * (GANMRES_MAX_WINDOW + 1) * kMaxSeg);
+            coef_dev = static_cast<double*>(bufs.back()->p);
         }
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * 128, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * kRes, hipHostMallocDefault));
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hup), sizeof(double) * (GANMRES_MAX_WINDOW + 1) * kMaxSeg,
+                             hipHostMallocDefault));
+        for (int i = 0; i < nb; ++i) hup[i] = alpha_s[i];
+        HIPCHK(hipMemcpyAsync(alpha_dev, hup, sizeof(double) * nb, hipMemcpyHostToDevice, st));
         HIPCHK(hipMemcpyAsync(m0, m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(m1, m1_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(mstate(0), m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
@@ -379,6 +418,7 @@ class Problem : public ProblemBase {
 
     ~Problem() override {
         if (hres) (void)hipHostFree(hres);
+        if (hup) (void)hipHostFree(hup);
         for (auto& e : ev_pool) {
             (void)hipEventDestroy(e.first);
             (void)hipEventDestroy(e.second);
@@ -433,11 +473,15 @@ class Problem : public ProblemBase {
         tend();
     }
 
-    double fetch(int nvals = 1) {
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * nvals, hipMemcpyDeviceToHost, st));
+    // copy result slot [at, at + n) to the host (synchronises)
+    const double* fetch(int at, int n) {
+        HIPCHK(hipMemcpyAsync(hres + at, dres + at, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        return hres[0];
+        return hres + at;
     }
+    // scalar and velocity fields as segments (one per stacked problem)
+    Seg sseg() const { return Seg{nb, 1, Nt, N}; }
+    Seg vseg() const { return Seg{nb, d, Nt, N}; }
 
     const T* comp(const void* v, int c) const { return static_cast<const T*>(v) + c * N; }
     T* comp(void* v, int c) const { return static_cast<T*>(v) + c * N; }
@@ -448,17 +492,18 @@ class Problem : public ProblemBase {
         s.p = cfg.reg_order;
         s.alpha = cfg.alpha;
         s.leray = leray ? 1 : 0;
+        s.alpha_seg = nb > 1 ? alpha_dev : nullptr;
         return s;
     }
 
     // -- per-velocity preparation ---------------------------------------------
-    // v^, R(v) (device scalar -> reg_cached), divergence, departure points and
+    // v^, R(v) (device sums per problem -> reg_s), divergence, departure points and
     // stationary source factors.
     void spectrum_of(const void* v) {
         const T* vin[3] = {comp(v, 0), comp(v, 1), d == 3 ? comp(v, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vh, d, st); });
         run(KC_REDUCE, [&] {
-            return launch_spec_regvalue<double>(dm, specop(false), vh, partial, dres + 64, st);
+            return launch_spec_regvalue<double>(dm, specop(false), vh, partial, dres + R_REG, st);
         });
         vh_of = v;
         reg_from_device = true;
@@ -471,12 +516,13 @@ class Problem : public ProblemBase {
         dbound = displacement_bound(um, d);
     }
 
-    // max |u| of a velocity (reduction + sync)
+    // max |u| of a velocity over all problems (reduction + sync)
     double velocity_max(const void* v) {
         run(KC_REDUCE, [&] {
-            return launch_velocity_max<T>(dm, static_cast<const T*>(v), cscale, partial, dres, st);
+            return launch_velocity_max<T>(dm, static_cast<const T*>(v), cscale, partial,
+                                          dres + R_UMAX, st);
         });
-        return fetch();
+        return fetch(R_UMAX, 1)[0];
     }
 
     // trial = true: a line-search trial whose R(v) the caller supplies and
@@ -545,32 +591,41 @@ class Problem : public ProblemBase {
             });
     }
 
-    // mismatch sum -> dres[0]; optionally lam^nt = m1 - m^nt
+    // mismatch sums per problem -> dres[R_MIS..]; optionally lam^nt = m1 - m^nt
     void mismatch(bool write_lam) {
         run(KC_REDUCE, [&] {
-            return launch_sumsq_diff<T>(mstate(cfg.nt), m1, write_lam ? lam_nt : nullptr, N,
-                                        partial, dres, st);
+            return launch_sumsq_diff<T>(mstate(cfg.nt), m1, write_lam ? lam_nt : nullptr, sseg(),
+                                        partial, dres + R_MIS, st);
         });
     }
 
+    // J per problem (J_s, mis_s) and their sum
     double finish_J(double* mis_out) {
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 128, hipMemcpyDeviceToHost, st));
+        const int n = reg_from_device ? R_REG + nb : nb;
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        const double mis = 0.5 * cell * hres[0];
-        if (reg_from_device) reg_cached = cell / double(N) * hres[64];
-        if (mis_out) *mis_out = mis;
-        return mis + 0.5 * cfg.alpha * reg_cached;
+        double Jt = 0.0, mt = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            mis_s[i] = 0.5 * cell * hres[R_MIS + i];
+            if (reg_from_device) reg_s[i] = cell / double(Nt) * hres[R_REG + i];
+            J_s[i] = mis_s[i] + 0.5 * alpha_s[i] * reg_s[i];
+            Jt += J_s[i];
+            mt += mis_s[i];
+        }
+        reg_from_device = false;
+        if (mis_out) *mis_out = mt;
+        return Jt;
     }
 
-    // J at a line-search trial v with a known regulariser value R
-    double objective_trial(const void* v, double R, double um) {
+    // J at a line-search trial v with known regulariser values R (per problem)
+    double objective_trial(const void* v, const std::vector<double>& R, double um) {
         prepare(v, false, true, um);
         forward();
         mismatch(false);
         fwd_valid = true;
         fwd_v = v;
         adj_valid = false;
-        reg_cached = R;
+        reg_s = R;
         reg_from_device = false;
         return finish_J(nullptr);
     }
@@ -687,13 +742,20 @@ class Problem : public ProblemBase {
             return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vh, wh, wh, st);
         });
         T* gout[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
-        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / N, d, st); });
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / Nt, d, st); });
         return J;
     }
 
-    double precond(const void* g, void* s) override { return precond_keep(g, s, false); }
+    double precond(const void* g, void* s) override {
+        precond_keep(g, s, false);
+        double t = 0.0;
+        for (int i = 0; i < nb; ++i) t += gs_s[i];
+        return t;
+    }
 
-    double precond_keep(const void* g, void* s, bool keep) {
+    // s = -(alpha L)^-1 g; gs_s = <g, s>_h per problem; keep: also keep s^
+    // and max |s| (cells per step)
+    void precond_keep(const void* g, void* s, bool keep) {
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
         run(KC_SPEC, [&] {
@@ -701,26 +763,31 @@ class Problem : public ProblemBase {
                                           keep ? sk : nullptr, st);
         });
         T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
-        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / N, d, st); });
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / Nt, d, st); });
         run(KC_REDUCE, [&] {
-            return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), d * N, partial,
-                                 dres, st);
+            return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), vseg(), partial,
+                                 dres + R_DOT, st);
         });
         if (keep)
             run(KC_REDUCE, [&] {
-                return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial, dres + 2,
-                                              st);
+                return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial,
+                                              dres + R_SMAX, st);
             });
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 3, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT, sizeof(double) * (R_SMAX + 1 - R_DOT),
+                              hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        smax = hres[2];
-        return cell * hres[0];
+        if (keep) smax = hres[R_SMAX];
+        gs_s.resize(nb);
+        for (int i = 0; i < nb; ++i) gs_s[i] = cell * hres[R_DOT + i];
     }
-    double smax = 0.0;  // max |u| of the last kept search direction
+    double smax = 0.0;          // max |u| of the last kept search direction
+    std::vector<double> gs_s;   // <g, s>_h per problem of the last preconditioning
 
-    double maxabs(const T* a) {
-        run(KC_REDUCE, [&] { return launch_maxabs<T>(a, d * N, partial, dres, st); });
-        return fetch();
+    // max |a| per problem
+    std::vector<double> maxabs(const T* a) {
+        run(KC_REDUCE, [&] { return launch_maxabs<T>(a, vseg(), partial, dres + R_MAX, st); });
+        const double* r = fetch(R_MAX, nb);
+        return std::vector<double>(r, r + nb);
     }
 
     void get_field(int which, int j, void* out) override {
@@ -739,12 +806,20 @@ class Problem : public ProblemBase {
         HIPCHK(hipStreamSynchronize(st));
     }
 
+    int count() const override { return nb; }
+    void values(double* J, double* mis) const override {
+        for (int i = 0; i < nb; ++i) {
+            if (J) J[i] = J_s[i];
+            if (mis) mis[i] = mis_s[i];
+        }
+    }
+
     // -- GA-NGMRES ----------------------------------------------------------
     void reset() override {
         started = false;
         hist.clear();
         k = 0;
-        rho_bar = 1.0;
+        rho_bar.assign(nb, 1.0);
     }
 
     T* rv(int slot) { return static_cast<T*>(ring_v[slot]->p); }
@@ -790,135 +865,192 @@ class Problem : public ProblemBase {
         return p.variant == GANMRES_VARIANT_ALT ? (m < p.tau) : (m >= p.sigma);
     }
 
-    // Armijo line search from the current iterate (Vc, Gc, Jcur); the accepted
-    // trial is left in qb with its forward solve kept (eqs. e:rpgd, e:armijo).
-    // Along the line the regulariser is a quadratic in rho:
+    // Armijo line search from the current iterate (Vc, Gc, Jcur), each stacked
+    // problem with its own step; the accepted trials are left in qb with
+    // their forward solve kept (eqs. e:rpgd, e:armijo).  Along the line the
+    // regulariser is a quadratic in rho:
     // R(v + rho s) = R(v) + 2 rho <v,L s>_h + rho^2 <s,L s>_h, and the spectrum
-    // of the accepted trial is v^ + rho s^; trials need no transform of their own.
-    double line_search(T* Vc, T* Gc, const ganmres_solver_params& p, ganmres_step_info& info,
-                       double& Jq) {
+    // of the accepted trial is v^ + rho s^; trials need no transform of their
+    // own.  Returns the accepted steps; Jq receives J(q) per problem.
+    std::vector<double> line_search(T* Vc, T* Gc, const ganmres_solver_params& p,
+                                    ganmres_step_info* info, std::vector<double>& Jq) {
         T* q = static_cast<T*>(qb->p);
         T* s = static_cast<T*>(sb->p);
         if (vh_of != Vc) {
             spectrum_of(Vc);
-            HIPCHK(hipMemcpyAsync(hres, dres + 64, sizeof(double), hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
-            reg_cached = cell / double(N) * hres[0];
+            const double* r = fetch(R_REG, nb);
+            for (int i = 0; i < nb; ++i) reg_s[i] = cell / double(Nt) * r[i];
+            reg_from_device = false;
         }
         if (umax_of != Vc) set_bounds(Vc, velocity_max(Vc));
-        const double R0 = reg_cached, um0 = umax;
-        const double gs = precond_keep(Gc, s, true);
-        run(KC_REDUCE, [&] { return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres, st); });
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        const double cA = cell / double(N) * hres[0], cB = cell / double(N) * hres[1];
-        double rho = rho_bar, Rq = R0;
-        int trials = 0;
-        bool accepted = false;
-        for (int t = 0; t <= p.max_backtracks; ++t) {
-            Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
-            const double bound = Jcur + p.c_armijo * rho * gs;
-            ++trials;
-            // J(q) = mismatch + alpha/2 R(q) with mismatch >= 0: a trial whose
-            // regulariser term alone reaches the Armijo bound fails whatever
-            // its transport gives (the same expression as in finish_J, so the
-            // decision is the one the full evaluation would take)
-            if (0.5 * cfg.alpha * Rq >= bound) {
-                rho *= 0.5;
-                continue;
-            }
-            run(KC_VEC, [&] { return launch_axpy<T>(Vc, rho, s, q, d * N, st); });
-            Jq = objective_trial(q, Rq, um0 + rho * smax);
-            if (Jq < bound) {
-                rho_bar = (t == 0) ? 2.0 * rho : rho;
-                if (p.rho_cap > 0.0) rho_bar = std::min(rho_bar, p.rho_cap);
-                accepted = true;
-                break;
-            }
-            rho *= 0.5;
+        const std::vector<double> R0 = reg_s;
+        const double um0 = umax;
+        precond_keep(Gc, s, true);
+        run(KC_REDUCE, [&] {
+            return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
+        });
+        const double* cr = fetch(R_CROSS, 2 * nb);
+        std::vector<double> cA(nb), cB(nb);
+        for (int i = 0; i < nb; ++i) {
+            cA[i] = cell / double(Nt) * cr[i];
+            cB[i] = cell / double(Nt) * cr[nb + i];
         }
-        info.n_trials = trials;
-        if (!accepted) throw Error(GANMRES_ELINESEARCH, "Armijo condition not met");
-        run(KC_SPEC, [&] { return launch_spec_axpy<T>(dm, d, vh, rho, sk, st); });
+        std::vector<double> rho(rho_bar), Rq(R0);
+        std::vector<int> trials(nb, 0);
+        std::vector<char> done(nb, 0);
+        Jq.assign(nb, 0.0);
+        int open = nb;
+        for (int t = 0; t <= p.max_backtracks && open > 0; ++t) {
+            std::vector<double> bound(nb, 0.0);
+            bool transport = false;
+            for (int i = 0; i < nb; ++i) {
+                if (done[i]) continue;
+                Rq[i] = R0[i] + 2.0 * rho[i] * cA[i] + rho[i] * rho[i] * cB[i];
+                bound[i] = Jcur[i] + p.c_armijo * rho[i] * gs_s[i];
+                ++trials[i];
+                // J(q) = mismatch + alpha/2 R(q) with mismatch >= 0: a trial
+                // whose regulariser term alone reaches the Armijo bound fails
+                // whatever its transport gives (the same expression as in
+                // finish_J, so the decision is the one the full evaluation
+                // would take)
+                if (0.5 * alpha_s[i] * Rq[i] >= bound[i]) {
+                    rho[i] *= 0.5;
+                    bound[i] = -INFINITY;  // decided
+                } else {
+                    transport = true;
+                }
+            }
+            if (!transport) continue;
+            run(KC_VEC, [&] { return launch_axpy<T>(Vc, rho.data(), s, q, vseg(), st); });
+            double rmax = 0.0;
+            for (int i = 0; i < nb; ++i) rmax = std::max(rmax, rho[i]);
+            objective_trial(q, Rq, um0 + rmax * smax);
+            for (int i = 0; i < nb; ++i) {
+                if (done[i] || bound[i] == -INFINITY) continue;
+                if (J_s[i] < bound[i]) {
+                    Jq[i] = J_s[i];
+                    rho_bar[i] = (trials[i] == 1) ? 2.0 * rho[i] : rho[i];
+                    if (p.rho_cap > 0.0) rho_bar[i] = std::min(rho_bar[i], p.rho_cap);
+                    done[i] = 1;
+                    --open;
+                } else {
+                    rho[i] *= 0.5;
+                }
+            }
+        }
+        for (int i = 0; i < nb; ++i) info[i].n_trials = trials[i];
+        if (open > 0) throw Error(GANMRES_ELINESEARCH, "Armijo condition not met");
+        run(KC_SPEC, [&] { return launch_spec_axpy<T>(dm, d, vh, rho.data(), sk, st); });
         vh_of = q;
-        reg_cached = Rq;
+        reg_s = Rq;
         reg_from_device = false;
         return rho;
     }
 
-    // least-squares coefficients from the FP64 Gram matrix of vecs[0..K)
+    // least-squares coefficients per problem from the FP64 Gram matrices of
+    // vecs[0..K): beta[i * K .. ] is the solution of problem i (K <= 8 vectors
+    // in one reduction; more in pairwise dots)
     std::vector<double> gram_lsq(const std::vector<const T*>& vecs) {
         const int K = (int)vecs.size();
-        std::vector<double> G(K * K);
+        const int np = K * (K + 1) / 2;
+        std::vector<double> G(np * nb);
         if (K <= 8) {
-            run(KC_REDUCE, [&] { return launch_gram<T>(vecs.data(), K, d * N, partial, dres, st); });
-            const int np = K * (K + 1) / 2;
-            HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * np, hipMemcpyDeviceToHost, st));
-            HIPCHK(hipStreamSynchronize(st));
+            run(KC_REDUCE, [&] {
+                return launch_gram<T>(vecs.data(), K, vseg(), partial, dres + R_GRAM, st);
+            });
+            const double* r = fetch(R_GRAM, np * nb);
+            for (int x = 0; x < np * nb; ++x) G[x] = r[x];
+        } else {
             int qi = 0;
             for (int a = 0; a < K; ++a)
-                for (int bb = a; bb < K; ++bb) G[a * K + bb] = G[bb * K + a] = hres[qi++];
-        } else {
-            for (int a = 0; a < K; ++a)
-                for (int bb = a; bb < K; ++bb) {
-                    run(KC_REDUCE, [&] { return launch_dot<T>(vecs[a], vecs[bb], d * N, partial, dres, st); });
-                    G[a * K + bb] = G[bb * K + a] = fetch();
+                for (int bb = a; bb < K; ++bb, ++qi) {
+                    run(KC_REDUCE, [&] {
+                        return launch_dot<T>(vecs[a], vecs[bb], vseg(), partial, dres + R_DOT, st);
+                    });
+                    const double* r = fetch(R_DOT, nb);
+                    for (int i = 0; i < nb; ++i) G[qi * nb + i] = r[i];
                 }
         }
-        std::vector<double> beta = lsq_from_gram(K, G);
-        for (double x : beta)
-            if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
+        std::vector<double> beta;
+        std::vector<double> Gi(K * K);
+        for (int i = 0; i < nb; ++i) {
+            int qi = 0;
+            for (int a = 0; a < K; ++a)
+                for (int bb = a; bb < K; ++bb, ++qi) Gi[a * K + bb] = Gi[bb * K + a] = G[qi * nb + i];
+            const std::vector<double> bi = lsq_from_gram(K, Gi);
+            for (double x : bi)
+                if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
+            beta.insert(beta.end(), bi.begin(), bi.end());
+        }
         return beta;
     }
 
-    void finish_step(const ganmres_solver_params& p, void* v, T* Vn, T* Gn, double Jnew,
-                     double Jq, double rho, int ngrad, ganmres_step_info& info) {
+    // out = q + sum_k coef_i[k] (q - xs[k]) with the coefficients of problem i
+    // at beta[i * K + k]
+    void combine(const T* q, const std::vector<const T*>& xs, const std::vector<double>& beta,
+                 int K, T* out) {
+        for (int kk = 0; kk < K; ++kk)
+            for (int i = 0; i < nb; ++i) hup[kk * nb + i] = beta[i * K + kk];
+        HIPCHK(hipMemcpyAsync(coef_dev, hup, sizeof(double) * K * nb, hipMemcpyHostToDevice, st));
+        run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), coef_dev, K, out, vseg(), st); });
+        // hup is reused by the next upload only after this copy has run
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    void finish_step(const ganmres_solver_params& p, void* v, T* Vn, T* Gn,
+                     const std::vector<double>& Jnew, const std::vector<double>& Jq,
+                     const std::vector<double>& rho, int ngrad, ganmres_step_info* info) {
         ++k;
-        const double ginf = maxabs(Gn);
-        Jcur = Jnew;
+        const std::vector<double> ginf = maxabs(Gn);
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
-        info.k = k;
-        info.J = Jnew;
-        info.J_q = Jq;
-        info.ginf = ginf;
-        info.g0inf = g0inf;
-        info.rho = rho;
-        info.n_grad = ngrad;
-        info.stop = (ginf <= p.eps_rel * g0inf) || (k >= p.n_iter);
-        if (!std::isfinite(Jnew) || !std::isfinite(ginf))
-            throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient");
+        bool finite = true;
+        for (int i = 0; i < nb; ++i) {
+            Jcur[i] = Jnew[i];
+            info[i].k = k;
+            info[i].J = Jnew[i];
+            info[i].J_q = Jq[i];
+            info[i].ginf = ginf[i];
+            info[i].g0inf = g0inf[i];
+            info[i].rho = rho[i];
+            info[i].n_grad = ngrad;
+            info[i].stop = (ginf[i] <= p.eps_rel * g0inf[i]) || (k >= p.n_iter);
+            finite = finite && std::isfinite(Jnew[i]) && std::isfinite(ginf[i]);
+        }
+        if (!finite) throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient");
     }
 
     void start(const ganmres_solver_params& p, void* v, T* V0, T* G0, int& ngrad) {
         HIPCHK(hipMemcpyAsync(V0, v, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
-        Jcur = gradient(V0, G0, false);
+        gradient(V0, G0, false);
         ++ngrad;
+        Jcur = J_s;
         g0inf = maxabs(G0);
-        if (!std::isfinite(Jcur) || !std::isfinite(g0inf))
-            throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient at v^0");
+        for (int i = 0; i < nb; ++i)
+            if (!std::isfinite(Jcur[i]) || !std::isfinite(g0inf[i]))
+                throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient at v^0");
         k = 0;
-        rho_bar = 1.0;
+        rho_bar.assign(nb, 1.0);
         started = true;
     }
 
-    void step(const ganmres_solver_params& p, void* v, ganmres_step_info& info) override {
+    void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) override {
         ensure_solver(p.w, p.accel);
-        info = ganmres_step_info{};
+        for (int i = 0; i < nb; ++i) info[i] = ganmres_step_info{};
         if (p.accel == GANMRES_ACCEL_AA) step_aa(p, v, info);
         else step_ngmres(p, v, info);
     }
 
     // One iteration of GA-NGMRES(w; sigma, tau) (Alg. 3).
-    void step_ngmres(const ganmres_solver_params& p, void* v, ganmres_step_info& info) {
+    void step_ngmres(const ganmres_solver_params& p, void* v, ganmres_step_info* info) {
         int ngrad = 0;
         if (!started) {
             start(p, v, rv(0), rg(0), ngrad);
             hist.assign(1, 0);
         }
         const int cur = hist.back();
-        double Jq = 0.0;
-        const double rho = line_search(rv(cur), rg(cur), p, info, Jq);
+        std::vector<double> Jq;
+        const std::vector<double> rho = line_search(rv(cur), rg(cur), p, info, Jq);
         T* q = static_cast<T*>(qb->p);
         T* gq = static_cast<T*>(gqb->p);
         gradient(q, gq, true);
@@ -930,12 +1062,12 @@ class Problem : public ProblemBase {
                 slot = i;
                 break;
             }
-        double Jnew;
+        std::vector<double> Jnew;
         if (is_fp(k, p)) {
             std::swap(ring_v[slot], qb);
             std::swap(ring_g[slot], gqb);
             Jnew = Jq;
-            info.step_kind = GANMRES_STEP_FP;
+            for (int i = 0; i < nb; ++i) info[i].step_kind = GANMRES_STEP_FP;
         } else {
             const int wk = std::min(k, p.w);
             std::vector<const T*> vecs(wk + 2);
@@ -944,12 +1076,16 @@ class Problem : public ProblemBase {
             const std::vector<double> beta = gram_lsq(vecs);
             std::vector<const T*> xs(wk + 1);
             for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
-            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), beta.data(), wk + 1, rv(slot), d * N, st); });
-            Jnew = gradient(rv(slot), rg(slot), false);
+            combine(q, xs, beta, wk + 1, rv(slot));
+            gradient(rv(slot), rg(slot), false);
+            Jnew = J_s;
             ++ngrad;
-            info.step_kind = GANMRES_STEP_NGMRES;
-            info.n_beta = wk + 1;
-            for (int i = 0; i <= wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = beta[i];
+            for (int i = 0; i < nb; ++i) {
+                info[i].step_kind = GANMRES_STEP_NGMRES;
+                info[i].n_beta = wk + 1;
+                for (int j = 0; j <= wk && j <= GANMRES_MAX_WINDOW; ++j)
+                    info[i].beta[j] = beta[i * (wk + 1) + j];
+            }
         }
         hist.push_back(slot);
         while ((int)hist.size() > p.w + 1) hist.pop_front();
@@ -959,7 +1095,7 @@ class Problem : public ProblemBase {
     // One iteration of GA-AA(w; sigma, tau): Alg. 2 with the alternation of
     // Alg. 3.  Ring slots hold (r, q) = (v - q(v), q(v)); slots 0/1 of the
     // (v, g) ring alternate as the current and the next iterate.
-    void step_aa(const ganmres_solver_params& p, void* v, ganmres_step_info& info) {
+    void step_aa(const ganmres_solver_params& p, void* v, ganmres_step_info* info) {
         int ngrad = 0;
         if (!started) {
             start(p, v, rv(0), rg(0), ngrad);
@@ -969,8 +1105,8 @@ class Problem : public ProblemBase {
         T* Vc = rv(aa_cur);
         T* Gc = rg(aa_cur);
         const int nxt = 1 - aa_cur;
-        double Jq = 0.0;
-        const double rho = line_search(Vc, Gc, p, info, Jq);
+        std::vector<double> Jq;
+        const std::vector<double> rho = line_search(Vc, Gc, p, info, Jq);
         T* q = static_cast<T*>(qb->p);
         const int wk = std::min(k, p.w);
         // the free (r, q) slot
@@ -981,16 +1117,18 @@ class Problem : public ProblemBase {
                 break;
             }
         if (slot >= 0) {
-            run(KC_VEC, [&] { return launch_axpy<T>(Vc, -1.0, q, ar(slot), d * N, st); });
+            const std::vector<double> minus(nb, -1.0);
+            run(KC_VEC, [&] { return launch_axpy<T>(Vc, minus.data(), q, ar(slot), vseg(), st); });
             HIPCHK(hipMemcpyAsync(aq(slot), q, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         }
-        double Jnew;
+        std::vector<double> Jnew;
         if (is_fp(k, p) || wk == 0) {
             // v^{k+1} = q: the trial buffer becomes the next iterate, and its
             // forward solve from the line search is reused
             std::swap(ring_v[nxt], qb);
-            Jnew = gradient(rv(nxt), rg(nxt), true);
-            info.step_kind = GANMRES_STEP_FP;
+            gradient(rv(nxt), rg(nxt), true);
+            Jnew = J_s;
+            for (int i = 0; i < nb; ++i) info[i].step_kind = GANMRES_STEP_FP;
         } else {
             std::vector<const T*> vecs(wk + 1);
             vecs[0] = ar(slot);
@@ -998,11 +1136,14 @@ class Problem : public ProblemBase {
             const std::vector<double> xi = gram_lsq(vecs);
             std::vector<const T*> xs(wk);
             for (int i = 1; i <= wk; ++i) xs[i - 1] = aq(hist[hist.size() - i]);
-            run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), xi.data(), wk, rv(nxt), d * N, st); });
-            Jnew = gradient(rv(nxt), rg(nxt), false);
-            info.step_kind = GANMRES_STEP_AA;
-            info.n_beta = wk;
-            for (int i = 0; i < wk && i <= GANMRES_MAX_WINDOW; ++i) info.beta[i] = xi[i];
+            combine(q, xs, xi, wk, rv(nxt));
+            gradient(rv(nxt), rg(nxt), false);
+            Jnew = J_s;
+            for (int i = 0; i < nb; ++i) {
+                info[i].step_kind = GANMRES_STEP_AA;
+                info[i].n_beta = wk;
+                for (int j = 0; j < wk && j <= GANMRES_MAX_WINDOW; ++j) info[i].beta[j] = xi[i * wk + j];
+            }
         }
         ++ngrad;
         if (slot >= 0) {
@@ -1048,10 +1189,8 @@ static int guarded(ganmres_handle* h, F&& f) {
     }
 }
 
-extern "C" {
-
-int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, void* stream,
-                   ganmres_handle** out) {
+static int create_impl(const ganmres_config* cfg, int count, const double* alpha, const void* m0,
+                       const void* m1, void* stream, ganmres_handle** out) {
     if (!cfg || !m0 || !m1 || !out) {
         g_create_error = "null argument";
         return GANMRES_EINVAL;
@@ -1059,6 +1198,10 @@ int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, vo
     *out = nullptr;
     const ganmres_config& c = *cfg;
     std::string why;
+    if (count < 1 || count > gan::kMaxSeg) why = "count must be in [1, 64]";
+    if (why.empty() && count > 1 && c.dim != 2) why = "batches stack 2-D problems";
+    for (int i = 0; alpha && i < count && why.empty(); ++i)
+        if (!(alpha[i] > 0.0)) why = "alpha must be > 0";
     if (c.dim != 2 && c.dim != 3) why = "dim must be 2 or 3";
     for (int a = 0; a < c.dim && why.empty(); ++a)
         if (!gan::size_ok(c.n[a])) why = "grid sizes must be 2^a 3^b in [4, 1024]";
@@ -1080,8 +1223,8 @@ int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, vo
     h->dtype = c.dtype;
     const int rc = guarded(h, [&] {
         hipStream_t st = static_cast<hipStream_t>(stream);
-        if (c.dtype == GANMRES_F32) h->impl.reset(new gan::Problem<float>(c, m0, m1, st));
-        else h->impl.reset(new gan::Problem<double>(c, m0, m1, st));
+        if (c.dtype == GANMRES_F32) h->impl.reset(new gan::Problem<float>(c, m0, m1, st, count, alpha));
+        else h->impl.reset(new gan::Problem<double>(c, m0, m1, st, count, alpha));
     });
     if (rc != GANMRES_OK) {
         g_create_error = h->err;
@@ -1090,6 +1233,25 @@ int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, vo
     }
     *out = h;
     return GANMRES_OK;
+}
+
+extern "C" {
+
+int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, void* stream,
+                   ganmres_handle** out) {
+    return create_impl(cfg, 1, nullptr, m0, m1, stream, out);
+}
+
+int ganmres_create_batch(const ganmres_config* cfg, int count, const double* alpha, const void* m0,
+                         const void* m1, void* stream, ganmres_handle** out) {
+    return create_impl(cfg, count, alpha, m0, m1, stream, out);
+}
+
+int ganmres_batch_count(const ganmres_handle* h) { return h ? h->impl->count() : 0; }
+
+int ganmres_batch_values(ganmres_handle* h, double* J, double* mismatch) {
+    if (!h || (!J && !mismatch)) return GANMRES_EINVAL;
+    return guarded(h, [&] { h->impl->values(J, mismatch); });
 }
 
 int ganmres_destroy(ganmres_handle* h) {
@@ -1144,8 +1306,15 @@ int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
         h->err = "invalid solver parameters";
         return GANMRES_EINVAL;
     }
-    ganmres_step_info local;
-    return guarded(h, [&] { h->impl->step(*p, v, info ? *info : local); });
+    std::vector<ganmres_step_info> local;
+    return guarded(h, [&] {
+        if (!info) {
+            local.resize(h->impl->count());
+            h->impl->step(*p, v, local.data());
+        } else {
+            h->impl->step(*p, v, info);
+        }
+    });
 }
 
 int ganmres_solver_reset(ganmres_handle* h) {

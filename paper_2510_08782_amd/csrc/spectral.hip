@@ -389,12 +389,24 @@ __device__ inline KVec kvec(const Dims& dm, long long lin) {
     const int i1 = (int)(rest % dm.n[1]);
     const int i0 = (int)(rest / dm.n[1]);
     KVec kv;
-    const int k0 = wavenumber(i0, dm.n[0]), k1 = wavenumber(i1, dm.n[1]), k2 = i2;
+    // 2-D: axis 0 stacks independent problems and carries no wavenumber
+    const int k0 = dm.dim == 3 ? wavenumber(i0, dm.n[0]) : 0;
+    const int k1 = wavenumber(i1, dm.n[1]), k2 = i2;
     kv.k2 = double(k0) * k0 + double(k1) * k1 + double(k2) * k2;
-    kv.kt[0] = wavenumber_odd(i0, dm.n[0]);
+    kv.kt[0] = dm.dim == 3 ? wavenumber_odd(i0, dm.n[0]) : 0.0;
     kv.kt[1] = wavenumber_odd(i1, dm.n[1]);
     kv.kt[2] = (2 * i2 == dm.n[2]) ? 0.0 : double(i2);
     return kv;
+}
+
+// Stacked problems (2-D batches): number of them and the one holding
+// half-spectrum element lin.
+__host__ __device__ inline int spec_nseg(const Dims& dm) { return dm.dim == 2 ? dm.n[0] : 1; }
+__device__ inline int spec_seg(const Dims& dm, long long lin) {
+    return dm.dim == 2 ? (int)(lin / ((long long)dm.n[1] * dm.n2h)) : 0;
+}
+__device__ inline double seg_alpha(const SpecOpParams& sp, const Dims& dm, long long lin) {
+    return sp.alpha_seg ? sp.alpha_seg[spec_seg(dm, lin)] : sp.alpha;
 }
 
 __device__ inline double ipow(double x, int p) {
@@ -430,7 +442,7 @@ __global__ void spec_gradient_kernel(Dims dm, SpecOpParams sp, SpecPtrs<double> 
     for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
          lin += (long long)gridDim.x * blockDim.x) {
         const KVec kv = kvec(dm, lin);
-        const double al = sp.alpha * ipow(kv.k2, sp.p);
+        const double al = seg_alpha(sp, dm, lin) * ipow(kv.k2, sp.p);
         C2<T> b[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) b[c] = c < sp.dim ? bh.spec[c][lin] : cmk(T(0), T(0));
@@ -452,7 +464,7 @@ __global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, Sp
         const KVec kv = kvec(dm, lin);
         double l = ipow(kv.k2, sp.p);
         if (l == 0.0) l = 1.0;
-        const T f = T(-1.0 / (sp.alpha * l));
+        const T f = T(-1.0 / (seg_alpha(sp, dm, lin) * l));
         C2<T> g[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
@@ -476,7 +488,8 @@ __global__ void __launch_bounds__(256) spec_cross_kernel(Dims dm, SpecOpParams s
                                                          double* partial) {
     __shared__ double red[256 / 64];
     double a = 0.0, b = 0.0;
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+    const long long len = dm.NH / gridDim.y, lo = blockIdx.y * len;
+    for (long long lin = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
          lin += (long long)gridDim.x * blockDim.x) {
         const KVec kv = kvec(dm, lin);
         const int i2 = (int)(lin % dm.n2h);
@@ -493,16 +506,17 @@ __global__ void __launch_bounds__(256) spec_cross_kernel(Dims dm, SpecOpParams s
     const double ra = block_reduce<false>(a, red);
     const double rb = block_reduce<false>(b, red);
     if (threadIdx.x == 0) {
-        partial[blockIdx.x] = ra;
-        partial[gridDim.x + blockIdx.x] = rb;
+        partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = ra;
+        partial[(long long)(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = rb;
     }
 }
 
 // vh[c] += rho * sh[c]  (FP64 spectrum of v updated along a line)
 template <typename T>
-__global__ void spec_axpy_kernel(Dims dm, int dim, SpecPtrs<double> vh, double rho, SpecPtrs<T> sh) {
+__global__ void spec_axpy_kernel(Dims dm, int dim, SpecPtrs<double> vh, SegCoef rc, SpecPtrs<T> sh) {
     for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
          lin += (long long)gridDim.x * blockDim.x) {
+        const double rho = rc.c[spec_seg(dm, lin)];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             if (c >= dim) continue;
@@ -520,7 +534,8 @@ __global__ void __launch_bounds__(256) spec_regvalue_kernel(Dims dm, SpecOpParam
                                                             SpecPtrs<T> vh, double* partial) {
     __shared__ double sh[256 / 64];
     double acc = 0.0;
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+    const long long len = dm.NH / gridDim.y, lo = blockIdx.y * len;
+    for (long long lin = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
          lin += (long long)gridDim.x * blockDim.x) {
         const KVec kv = kvec(dm, lin);
         const int i2 = (int)(lin % dm.n2h);
@@ -534,7 +549,15 @@ __global__ void __launch_bounds__(256) spec_regvalue_kernel(Dims dm, SpecOpParam
         acc += wgt * l * s;
     }
     const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = r;
+}
+
+// blocks per stacked problem of a spectral reduction of nq quantities
+inline int spec_red_blocks(const Dims& dm, int nq) {
+    const int ns = spec_nseg(dm);
+    int b = reduction_blocks(dm.NH / ns);
+    const int cap = (64 * 1024) / (nq * ns);
+    return b > cap ? (cap < 1 ? 1 : cap) : b;
 }
 
 inline int pointwise_blocks(long long n) {
@@ -686,14 +709,14 @@ hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>*
         a.spec[c] = vh[c];
         b.spec[c] = sh[c];
     }
-    const int nb = reduction_blocks(dm.NH);
-    spec_cross_kernel<T><<<nb, 256, 0, st>>>(dm, sp, a, b, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 2, res);
+    const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 2);
+    spec_cross_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, b, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 2 * ns, res);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, double rho,
+hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, const double* rho,
                             C2<T>* const* sh, hipStream_t st) {
     SpecPtrs<double> a{};
     SpecPtrs<T> b{};
@@ -701,7 +724,11 @@ hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, doub
         a.spec[c] = vh[c];
         b.spec[c] = sh[c];
     }
-    spec_axpy_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, dim, a, rho, b);
+    const int ns = spec_nseg(dm);
+    if (ns > kMaxSeg) return hipErrorInvalidValue;
+    SegCoef rc{};
+    for (int i = 0; i < ns; ++i) rc.c[i] = rho[i];
+    spec_axpy_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, dim, a, rc, b);
     return hipGetLastError();
 }
 
@@ -710,9 +737,9 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
                                 double* partial, double* res, hipStream_t st) {
     SpecPtrs<T> a{};
     for (int c = 0; c < sp.dim; ++c) a.spec[c] = vh[c];
-    const int nb = reduction_blocks(dm.NH);
-    spec_regvalue_kernel<T><<<nb, 256, 0, st>>>(dm, sp, a, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 1, res);
+    const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 1);
+    spec_regvalue_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, ns, res);
     return hipGetLastError();
 }
 
@@ -731,7 +758,7 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
                                                C2<T>* const*, C2<T>* const*, hipStream_t);        \
     template hipError_t launch_spec_cross<T>(const Dims&, const SpecOpParams&, C2<double>* const*, \
                                              C2<T>* const*, double*, double*, hipStream_t);       \
-    template hipError_t launch_spec_axpy<T>(const Dims&, int, C2<double>* const*, double,         \
+    template hipError_t launch_spec_axpy<T>(const Dims&, int, C2<double>* const*, const double*,  \
                                             C2<T>* const*, hipStream_t);                          \
     template hipError_t launch_spec_regvalue<T>(const Dims&, const SpecOpParams&, C2<T>* const*,  \
                                                 double*, double*, hipStream_t);

@@ -1,10 +1,13 @@
 // FP64-accumulated reductions and vector updates.
 //
-// Reductions are deterministic: stage 1 runs a fixed number of blocks
-// (a function of n only) with a grid-stride loop and a fixed
+// Reductions are deterministic: stage 1 runs a fixed number of blocks per
+// segment (a function of the sizes only) with a grid-stride loop and a fixed
 // wavefront-shuffle tree, writing one partial per block; stage 2 is a single
 // block that folds the partials in a fixed order.  Repeated calls on the same
-// data are therefore bitwise identical.
+// data are therefore bitwise identical.  Segments are the independent
+// problems of a batch (one segment for a single problem).
+#include <algorithm>
+
 #include "launch.hpp"
 #include "reduce.hpp"
 
@@ -14,51 +17,69 @@ namespace {
 
 constexpr int kRedThreads = 256;
 constexpr int kMaxRedBlocks = 1024;
+constexpr long long kPartialCap = 64 * 1024;  // doubles in the partials buffer
 
+// Element (c, s, i) of a segmented array (see Seg).
+__device__ inline long long seg_at(const Seg& g, int c, int s, long long i) {
+    return c * g.cstride + s * g.seglen + i;
+}
+
+// Every reduction kernel runs gridDim.y = nseg rows of gridDim.x blocks; block
+// (x, s) strides over segment s and writes partial[(q nseg + s) gridDim.x + x]
+// for its quantity q.
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) sumsq_diff_kernel(const T* __restrict__ a,
                                                                  const T* __restrict__ b,
-                                                                 T* __restrict__ lam, long long n,
+                                                                 T* __restrict__ lam, Seg g,
                                                                  double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
     double acc = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const T d = b[i] - a[i];
-        if (lam) lam[i] = d;
-        const double dd = static_cast<double>(d);
-        acc += dd * dd;
-    }
+    for (int c = 0; c < g.ncomp; ++c)
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+             i += (long long)gridDim.x * blockDim.x) {
+            const long long e = seg_at(g, c, s, i);
+            const T d = b[e] - a[e];
+            if (lam) lam[e] = d;
+            const double dd = static_cast<double>(d);
+            acc += dd * dd;
+        }
     const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
 }
 
 template <typename T>
 __global__ void __launch_bounds__(kRedThreads) dot_kernel(const T* __restrict__ a,
-                                                          const T* __restrict__ b, long long n,
+                                                          const T* __restrict__ b, Seg g,
                                                           double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
     double acc = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x)
-        acc += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+    for (int c = 0; c < g.ncomp; ++c)
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+             i += (long long)gridDim.x * blockDim.x) {
+            const long long e = seg_at(g, c, s, i);
+            acc += static_cast<double>(a[e]) * static_cast<double>(b[e]);
+        }
     const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kRedThreads) maxabs_kernel(const T* __restrict__ a, long long n,
+__global__ void __launch_bounds__(kRedThreads) maxabs_kernel(const T* __restrict__ a, Seg g,
                                                              double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
     double m = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        double x = fabs(static_cast<double>(a[i]));
-        if (!(x <= 1.0e308)) x = INFINITY;  // NaN and inf both count as inf
-        m = fmax(m, x);
-    }
+    for (int c = 0; c < g.ncomp; ++c)
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+             i += (long long)gridDim.x * blockDim.x) {
+            double x = fabs(static_cast<double>(a[seg_at(g, c, s, i)]));
+            if (!(x <= 1.0e308)) x = INFINITY;  // NaN and inf both count as inf
+            m = fmax(m, x);
+        }
     const double r = block_reduce<true>(m, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
 }
 
 template <typename T, int K>
@@ -67,55 +88,69 @@ struct VecList {
 };
 
 template <typename T, int K>
-__global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, long long n,
+__global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg g,
                                                            double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
     constexpr int NP = K * (K + 1) / 2;
+    const int s = blockIdx.y;
     double acc[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        double x[K];
+    for (int c = 0; c < g.ncomp; ++c)
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+             i += (long long)gridDim.x * blockDim.x) {
+            const long long e = seg_at(g, c, s, i);
+            double x[K];
 #pragma unroll
-        for (int a = 0; a < K; ++a) x[a] = static_cast<double>(vl.p[a][i]);
-        int q = 0;
+            for (int a = 0; a < K; ++a) x[a] = static_cast<double>(vl.p[a][e]);
+            int q = 0;
 #pragma unroll
-        for (int a = 0; a < K; ++a)
+            for (int a = 0; a < K; ++a)
 #pragma unroll
-            for (int b = a; b < K; ++b) acc[q++] += x[a] * x[b];
-    }
+                for (int b = a; b < K; ++b) acc[q++] += x[a] * x[b];
+        }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const double r = block_reduce<false>(acc[q], sh);
-        if (threadIdx.x == 0) partial[(long long)q * gridDim.x + blockIdx.x] = r;
+        if (threadIdx.x == 0)
+            partial[((long long)q * gridDim.y + s) * gridDim.x + blockIdx.x] = r;
     }
 }
 
+// Segment-wise vector updates: gridDim.y = ncomp * nseg rows, row y covers
+// component y / nseg of segment y % nseg.
 template <typename T>
-__global__ void axpy_kernel(const T* __restrict__ a, T s, const T* __restrict__ b,
-                            T* __restrict__ out, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+__global__ void axpy_kernel(const T* __restrict__ a, SegCoef sc, const T* __restrict__ b,
+                            T* __restrict__ out, Seg g) {
+    const int c = blockIdx.y / g.nseg, s = blockIdx.y % g.nseg;
+    const T k = T(sc.c[s]);
+    const long long base = c * g.cstride + s * g.seglen;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
          i += (long long)gridDim.x * blockDim.x)
-        out[i] = a[i] + s * b[i];
+        out[base + i] = a[base + i] + k * b[base + i];
 }
 
 constexpr int kMaxCombine = 65;
 template <typename T>
 struct CombineArgs {
     const T* x[kMaxCombine];
-    T c[kMaxCombine];
 };
 
+// out = q + sum_k coef[k nseg + s] (q - x_k) on segment s
 template <typename T>
-__global__ void combine_kernel(const T* __restrict__ q, CombineArgs<T> ca, int K,
-                               T* __restrict__ out, long long n) {
-    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+__global__ void combine_kernel(const T* __restrict__ q, CombineArgs<T> ca,
+                               const double* __restrict__ coef, int K, T* __restrict__ out,
+                               Seg g) {
+    const int c = blockIdx.y / g.nseg, s = blockIdx.y % g.nseg;
+    const long long base = c * g.cstride + s * g.seglen;
+    T cs[kMaxCombine];
+    for (int k = 0; k < K; ++k) cs[k] = T(coef[k * g.nseg + s]);
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
          i += (long long)gridDim.x * blockDim.x) {
-        const T qi = q[i];
+        const T qi = q[base + i];
         T acc = qi;
-        for (int k = 0; k < K; ++k) acc += ca.c[k] * (qi - ca.x[k][i]);
-        out[i] = acc;
+        for (int k = 0; k < K; ++k) acc += cs[k] * (qi - ca.x[k][base + i]);
+        out[base + i] = acc;
     }
 }
 
@@ -126,14 +161,31 @@ inline int stream_blocks(long long n) {
     return static_cast<int>(b);
 }
 
+// blocks per row of a segment-wise vector update (rows = ncomp * nseg)
+int row_blocks(const Seg& g) {
+    const int rows = g.ncomp * g.nseg;
+    int b = stream_blocks(g.seglen);
+    if ((long long)b * rows > 8192) b = std::max(1, 8192 / rows);
+    return b;
+}
+
+// blocks per segment for a reduction of nq quantities
+int seg_blocks(const Seg& g, int nq) {
+    long long b = reduction_blocks(g.ncomp * g.seglen);
+    const long long cap = kPartialCap / ((long long)nq * g.nseg);
+    if (b > cap) b = cap;
+    return static_cast<int>(b < 1 ? 1 : b);
+}
+
 template <typename T, int K>
-hipError_t gram_k(const T* const* vecs, long long n, double* partial, double* res,
+hipError_t gram_k(const T* const* vecs, const Seg& g, double* partial, double* res,
                   hipStream_t st) {
     VecList<T, K> vl;
     for (int a = 0; a < K; ++a) vl.p[a] = vecs[a];
-    const int nb = reduction_blocks(n);
-    gram_kernel<T, K><<<nb, kRedThreads, 0, st>>>(vl, n, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, K * (K + 1) / 2, res);
+    constexpr int NP = K * (K + 1) / 2;
+    const int nb = seg_blocks(g, NP);
+    gram_kernel<T, K><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(vl, g, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, NP * g.nseg, res);
     return hipGetLastError();
 }
 
@@ -146,80 +198,91 @@ int reduction_blocks(long long n) {
     return static_cast<int>(b);
 }
 
+bool seg_valid(const Seg& g) {
+    return g.nseg >= 1 && g.nseg <= kMaxSeg && g.ncomp >= 1 && g.seglen >= 1;
+}
+
 template <typename T>
-hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, long long n, double* partial,
+hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, const Seg& g, double* partial,
                              double* res, hipStream_t st) {
-    const int nb = reduction_blocks(n);
-    sumsq_diff_kernel<T><<<nb, kRedThreads, 0, st>>>(a, b, lam, n, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 1, res);
+    if (!seg_valid(g)) return hipErrorInvalidValue;
+    const int nb = seg_blocks(g, 1);
+    sumsq_diff_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, lam, g, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_dot(const T* a, const T* b, long long n, double* partial, double* res,
+hipError_t launch_dot(const T* a, const T* b, const Seg& g, double* partial, double* res,
                       hipStream_t st) {
-    const int nb = reduction_blocks(n);
-    dot_kernel<T><<<nb, kRedThreads, 0, st>>>(a, b, n, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 1, res);
+    if (!seg_valid(g)) return hipErrorInvalidValue;
+    const int nb = seg_blocks(g, 1);
+    dot_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, g, partial);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_maxabs(const T* a, long long n, double* partial, double* res, hipStream_t st) {
-    const int nb = reduction_blocks(n);
-    maxabs_kernel<T><<<nb, kRedThreads, 0, st>>>(a, n, partial);
-    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 1, res);
+hipError_t launch_maxabs(const T* a, const Seg& g, double* partial, double* res, hipStream_t st) {
+    if (!seg_valid(g)) return hipErrorInvalidValue;
+    const int nb = seg_blocks(g, 1);
+    maxabs_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, partial);
+    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
 // The packed Gram kernel writes the upper triangle in row order; the host
-// unpacks.  Here res receives K(K+1)/2 packed values.
+// unpacks.  res[q nseg + s] receives packed entry q of segment s.
 template <typename T>
-hipError_t launch_gram(const T* const* vecs, int K, long long n, double* partial, double* res,
+hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partial, double* res,
                        hipStream_t st) {
+    if (!seg_valid(g)) return hipErrorInvalidValue;
     switch (K) {
-        case 1: return gram_k<T, 1>(vecs, n, partial, res, st);
-        case 2: return gram_k<T, 2>(vecs, n, partial, res, st);
-        case 3: return gram_k<T, 3>(vecs, n, partial, res, st);
-        case 4: return gram_k<T, 4>(vecs, n, partial, res, st);
-        case 5: return gram_k<T, 5>(vecs, n, partial, res, st);
-        case 6: return gram_k<T, 6>(vecs, n, partial, res, st);
-        case 7: return gram_k<T, 7>(vecs, n, partial, res, st);
-        case 8: return gram_k<T, 8>(vecs, n, partial, res, st);
+        case 1: return gram_k<T, 1>(vecs, g, partial, res, st);
+        case 2: return gram_k<T, 2>(vecs, g, partial, res, st);
+        case 3: return gram_k<T, 3>(vecs, g, partial, res, st);
+        case 4: return gram_k<T, 4>(vecs, g, partial, res, st);
+        case 5: return gram_k<T, 5>(vecs, g, partial, res, st);
+        case 6: return gram_k<T, 6>(vecs, g, partial, res, st);
+        case 7: return gram_k<T, 7>(vecs, g, partial, res, st);
+        case 8: return gram_k<T, 8>(vecs, g, partial, res, st);
         default: return hipErrorInvalidValue;
     }
 }
 
 template <typename T>
-hipError_t launch_axpy(const T* a, double s, const T* b, T* out, long long n, hipStream_t st) {
-    axpy_kernel<T><<<stream_blocks(n), 256, 0, st>>>(a, T(s), b, out, n);
+hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Seg& g,
+                       hipStream_t st) {
+    if (!seg_valid(g)) return hipErrorInvalidValue;
+    SegCoef sc{};
+    for (int i = 0; i < g.nseg; ++i) sc.c[i] = s[i];
+    axpy_kernel<T><<<dim3(row_blocks(g), g.ncomp * g.nseg), 256, 0, st>>>(a, sc, b, out, g);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_combine(const T* q, const T* const* x, const double* c, int K, T* out,
-                          long long n, hipStream_t st) {
-    if (K < 0 || K > kMaxCombine) return hipErrorInvalidValue;
+hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int K, T* out,
+                          const Seg& g, hipStream_t st) {
+    if (K < 0 || K > kMaxCombine || !seg_valid(g)) return hipErrorInvalidValue;
     CombineArgs<T> ca;
-    for (int k = 0; k < kMaxCombine; ++k) {
-        ca.x[k] = k < K ? x[k] : nullptr;
-        ca.c[k] = k < K ? T(c[k]) : T(0);
-    }
-    combine_kernel<T><<<stream_blocks(n), 256, 0, st>>>(q, ca, K, out, n);
+    for (int k = 0; k < kMaxCombine; ++k) ca.x[k] = k < K ? x[k] : nullptr;
+    combine_kernel<T><<<dim3(row_blocks(g), g.ncomp * g.nseg), 256, 0, st>>>(q, ca, coef, K, out,
+                                                                           g);
     return hipGetLastError();
 }
 
-#define GAN_INST(T)                                                                             \
-    template hipError_t launch_sumsq_diff<T>(const T*, const T*, T*, long long, double*, double*, \
-                                             hipStream_t);                                      \
-    template hipError_t launch_dot<T>(const T*, const T*, long long, double*, double*,          \
-                                      hipStream_t);                                             \
-    template hipError_t launch_maxabs<T>(const T*, long long, double*, double*, hipStream_t);   \
-    template hipError_t launch_gram<T>(const T* const*, int, long long, double*, double*,       \
-                                       hipStream_t);                                            \
-    template hipError_t launch_axpy<T>(const T*, double, const T*, T*, long long, hipStream_t);  \
-    template hipError_t launch_combine<T>(const T*, const T* const*, const double*, int, T*,    \
-                                          long long, hipStream_t);
+#define GAN_INST(T)                                                                               \
+    template hipError_t launch_sumsq_diff<T>(const T*, const T*, T*, const Seg&, double*, double*,  \
+                                             hipStream_t);                                        \
+    template hipError_t launch_dot<T>(const T*, const T*, const Seg&, double*, double*,           \
+                                      hipStream_t);                                               \
+    template hipError_t launch_maxabs<T>(const T*, const Seg&, double*, double*, hipStream_t);    \
+    template hipError_t launch_gram<T>(const T* const*, int, const Seg&, double*, double*,        \
+                                       hipStream_t);                                              \
+    template hipError_t launch_axpy<T>(const T*, const double*, const T*, T*, const Seg&,         \
+                                       hipStream_t);                                              \
+    template hipError_t launch_combine<T>(const T*, const T* const*, const double*, int, T*,      \
+                                          const Seg&, hipStream_t);
 GAN_INST(float)
 GAN_INST(double)
 #undef GAN_INST

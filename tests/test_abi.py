@@ -10,11 +10,11 @@ import paper_2510_08782_amd as gan
 def test_library_exports_every_header_symbol():
     lib = gan.lib()
     syms = gan.header_symbols()
-    assert len(syms) == 15
+    assert len(syms) == 18
     for name in syms:
         assert hasattr(lib, name), name
     for name in ["ganmres_eval_objective", "ganmres_eval_gradient", "ganmres_apply_precond",
-                 "ganmres_step"]:
+                 "ganmres_step", "ganmres_create_batch"]:
         assert name in syms
 
 
@@ -50,8 +50,26 @@ def test_create_rejects_invalid_config_without_device_work(bad):
     assert not h.value
 
 
+@pytest.mark.parametrize("count,dim,alpha", [
+    (0, 2, None), (65, 2, None), (2, 3, None), (2, 2, (1e-2, 0.0)), (2, 2, (1e-2, -1.0)),
+])
+def test_create_batch_rejects_invalid_batches(count, dim, alpha):
+    n = (32, 32, 32) if dim == 3 else (32, 32, 1)
+    cfg = gan.Config(dim, (ctypes.c_int * 3)(*n), 4, gan.ADVECTION, 0, 1, 1e-2, gan.F64, 1)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)      # never dereferenced: validation fails first
+    al = (ctypes.c_double * len(alpha))(*alpha) if alpha else None
+    rc = gan.lib().ganmres_create_batch(ctypes.byref(cfg), count, al, dummy, dummy, None,
+                                        ctypes.byref(h))
+    assert rc == -1
+    assert gan.lib().ganmres_last_error(None)
+    assert not h.value
+
+
 def test_null_arguments_are_rejected():
     lib = gan.lib()
     assert lib.ganmres_eval_objective(None, None, 0, None, None) == -1
     assert lib.ganmres_step(None, None, None, None) == -1
     assert lib.ganmres_destroy(None) == 0
+    assert lib.ganmres_batch_count(None) == 0
+    assert lib.ganmres_batch_values(None, None, None) == -1

@@ -7,28 +7,32 @@
 namespace gan {
 
 // ---- semi-Lagrangian kernels (sl.hip) --------------------------------------
-// Displacement bounds are host ints, upper bounds on max |d| in cells; each
-// launcher picks the LDS halo variant that covers its bound.
+// Each launcher takes `spread`, a host bound on the spread of the
+// displacement floors over the field (cells: floor(B) + ceil(B) for a bound
+// B >= max |d|, see spread_bound), and picks the LDS window variant that
+// covers it.
 // max over components and points of |s_c v_c(i)| -> res[0] (FP64 reduction)
 template <typename T>
 hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, double* partial,
                                double* res, hipStream_t st);
-// Upper bound (cells) of the RK2 departure displacements given max |u|.
+// floor(B) + ceil(B): the spread of floor(d) over displacements |d| <= B
+int spread_bound(double B);
+// spread_bound of the RK2 departure displacements given max |u|
 int displacement_bound(double umax, int dim);
 // RK2 departure displacements (index units) for velocity +v (dX, nullable) and
 // -v (dY, nullable).  s[c] = h_t / h_c converts component c to cells per step;
-// ubound >= max |u|.
+// spread = spread_bound(max |u|).
 template <typename T>
-hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int ubound, T* dX,
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int spread, T* dX,
                                   T* dY, hipStream_t st);
-// out = [fac *] I[src](i + disp); bound >= max |disp|
+// out = [fac *] I[src](i + disp)
 template <typename T>
-hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int bound,
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int spread,
                           T* out, hipStream_t st);
 // out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, int bound, T* out, hipStream_t st);
+                                double sgn, int spread, T* out, hipStream_t st);
 
 // ---- reductions and vector kernels (vec.hip) -------------------------------
 // Arrays are segmented: a batch of nseg independent problems stacked along the

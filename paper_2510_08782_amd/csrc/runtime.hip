@@ -250,8 +250,9 @@ class Problem : public ProblemBase {
     std::vector<double> J_s, mis_s;
     // displacement bounds of the velocity whose departure points are current
     double umax = 0.0;              // >= max |u| (cells per step)
-    int ubound = 0, dbound = 0;     // ceil bounds for the predictor and for X / Y
+    int ubound = 0, dbound = 0;     // floor-spread bounds for the predictor and for X / Y
     const void* umax_of = nullptr;  // velocity umax belongs to
+    hipEvent_t ev_res = nullptr;  // marks a result copy the host waits for while later work runs
     double* hres = nullptr;  // pinned host results
     double* hup = nullptr;   // pinned staging of host -> device tables
     // slots of the device / host result buffers (per-problem values from s)
@@ -406,6 +407,7 @@ class Problem : public ProblemBase {
             coef_dev = static_cast<double*>(bufs.back()->p);
         }
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * kRes, hipHostMallocDefault));
+        HIPCHK(hipEventCreateWithFlags(&ev_res, hipEventDisableTiming));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hup), sizeof(double) * (GANMRES_MAX_WINDOW + 1) * kMaxSeg,
                              hipHostMallocDefault));
         for (int i = 0; i < nb; ++i) hup[i] = alpha_s[i];
@@ -417,6 +419,7 @@ class Problem : public ProblemBase {
     }
 
     ~Problem() override {
+        if (ev_res) (void)hipEventDestroy(ev_res);
         if (hres) (void)hipHostFree(hres);
         if (hup) (void)hipHostFree(hup);
         for (auto& e : ev_pool) {
@@ -512,7 +515,7 @@ class Problem : public ProblemBase {
     void set_bounds(const void* v, double um) {
         umax = um;
         umax_of = v;
-        ubound = !(um <= 1.0e6) ? (1 << 20) : static_cast<int>(std::ceil(um * (1.0 + 1e-6)));
+        ubound = spread_bound(um * (1.0 + 1e-6));
         dbound = displacement_bound(um, d);
     }
 
@@ -529,8 +532,22 @@ class Problem : public ProblemBase {
     // whose spectrum is not needed (vh keeps the current iterate's); umax_known
     // >= 0 is a known bound on max |u| of v (else it is reduced on the device)
     void prepare(const void* v, bool needY, bool trial = false, double umax_known = -1.0) {
-        if (!trial) spectrum_of(v);
-        set_bounds(v, umax_known >= 0.0 ? umax_known : velocity_max(v));
+        if (umax_known >= 0.0) {
+            if (!trial) spectrum_of(v);
+            set_bounds(v, umax_known);
+        } else {
+            // the bound picks the gather variants: reduce it first and let the
+            // spectrum of v run while the host waits for it
+            run(KC_REDUCE, [&] {
+                return launch_velocity_max<T>(dm, static_cast<const T*>(v), cscale, partial,
+                                              dres + R_UMAX, st);
+            });
+            HIPCHK(hipMemcpyAsync(hres + R_UMAX, dres + R_UMAX, sizeof(double), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipEventRecord(ev_res, st));
+            if (!trial) spectrum_of(v);
+            HIPCHK(hipEventSynchronize(ev_res));
+            set_bounds(v, hres[R_UMAX]);
+        }
         if (delta) {
             const double one = 1.0;
             for (int cc = 0; cc < d; ++cc) {
@@ -753,8 +770,9 @@ class Problem : public ProblemBase {
         return t;
     }
 
-    // s = -(alpha L)^-1 g; gs_s = <g, s>_h per problem; keep: also keep s^
-    // and max |s| (cells per step)
+    // s = -(alpha L)^-1 g; gs_s = <g, s>_h per problem; keep: also keep s^,
+    // max |s| (cells per step) and the regulariser cross terms of the line
+    // v + rho s (dres[R_CROSS..], see launch_spec_cross)
     void precond_keep(const void* g, void* s, bool keep) {
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
@@ -762,6 +780,10 @@ class Problem : public ProblemBase {
             return launch_spec_precond<T>(dm, specop(cfg.incompressible != 0), wh, wh,
                                           keep ? sk : nullptr, st);
         });
+        if (keep)
+            run(KC_REDUCE, [&] {
+                return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
+            });
         T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / Nt, d, st); });
         run(KC_REDUCE, [&] {
@@ -773,7 +795,8 @@ class Problem : public ProblemBase {
                 return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial,
                                               dres + R_SMAX, st);
             });
-        HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT, sizeof(double) * (R_SMAX + 1 - R_DOT),
+        HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT,
+                              sizeof(double) * ((keep ? R_CROSS + 2 * nb : R_SMAX + 1) - R_DOT),
                               hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (keep) smax = hres[R_SMAX];
@@ -886,10 +909,7 @@ class Problem : public ProblemBase {
         const std::vector<double> R0 = reg_s;
         const double um0 = umax;
         precond_keep(Gc, s, true);
-        run(KC_REDUCE, [&] {
-            return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
-        });
-        const double* cr = fetch(R_CROSS, 2 * nb);
+        const double* cr = hres + R_CROSS;
         std::vector<double> cA(nb), cB(nb);
         for (int i = 0; i < nb; ++i) {
             cA[i] = cell / double(Nt) * cr[i];
@@ -993,17 +1013,19 @@ class Problem : public ProblemBase {
             for (int i = 0; i < nb; ++i) hup[kk * nb + i] = beta[i * K + kk];
         HIPCHK(hipMemcpyAsync(coef_dev, hup, sizeof(double) * K * nb, hipMemcpyHostToDevice, st));
         run(KC_VEC, [&] { return launch_combine<T>(q, xs.data(), coef_dev, K, out, vseg(), st); });
-        // hup is reused by the next upload only after this copy has run
-        HIPCHK(hipStreamSynchronize(st));
+        // hup is next written by the following step's mixing, after several
+        // synchronisations of the stream: the copy has run by then
     }
 
     void finish_step(const ganmres_solver_params& p, void* v, T* Vn, T* Gn,
                      const std::vector<double>& Jnew, const std::vector<double>& Jq,
                      const std::vector<double>& rho, int ngrad, ganmres_step_info* info) {
         ++k;
-        const std::vector<double> ginf = maxabs(Gn);
+        run(KC_REDUCE, [&] { return launch_maxabs<T>(Gn, vseg(), partial, dres + R_MAX, st); });
+        HIPCHK(hipMemcpyAsync(hres + R_MAX, dres + R_MAX, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+        const std::vector<double> ginf(hres + R_MAX, hres + R_MAX + nb);
         bool finite = true;
         for (int i = 0; i < nb; ++i) {
             Jcur[i] = Jnew[i];

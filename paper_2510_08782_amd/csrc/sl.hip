@@ -402,7 +402,7 @@ __device__ inline T step_epilogue(T r, const T* __restrict__ src, const T* __res
 // LDS = true: tiles whose window fits (the others return at once);
 // LDS = false: the remaining tiles, every tap read from global memory.  Two
 // kernels, so that the LDS path does not carry the direct gather's registers;
-// the second is launched only when the displacement bound allows a tile to
+// the second is launched only when the spread bound allows a tile to
 // exceed the window.
 template <class C, int EPI, bool LDS>
 __global__ void __launch_bounds__(kThreads) sl_step_kernel(
@@ -648,39 +648,38 @@ __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restr
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
 
-// Variant choice from a bound b on |displacement| (cells): the floors then lie
-// in [-b, b], so a tile's spread is at most 2b, and the smallest capacity
-// covering 2b is taken; beyond the largest, the largest runs and only tiles
-// whose own spread exceeds it gather from global memory.
+// Variant choice from a bound on the spread of the displacement floors over
+// the field (cells; a displacement bound B gives floor(B) + ceil(B)): the
+// smallest capacity that covers it; beyond the largest, the largest runs and
+// only tiles whose own spread exceeds it gather from global memory.
 template <typename T, int DIM>
-int pick_capacity(int bound) {
-    const long long sp = 2LL * bound;
-    if (DIM == 2) return sp <= 8 ? 8 : 16;
-    if (sizeof(T) == 8) return sp <= 2 ? 2 : 4;
-    return sp <= 2 ? 2 : (sp <= 4 ? 4 : 8);
+int pick_capacity(int spread) {
+    if (DIM == 2) return spread <= 8 ? 8 : 16;
+    if (sizeof(T) == 8) return spread <= 2 ? 2 : (spread <= 3 ? 3 : 4);
+    return spread <= 2 ? 2 : (spread <= 3 ? 3 : (spread <= 4 ? 4 : 8));
 }
 
 template <class C, bool DOX, bool DOY>
-void char_launch(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+void char_launch(const Dims& dm, const typename C::T* v, const double* s, int spread,
                  typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
     const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
     characteristics_kernel<C, DOX, DOY, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
         dm, v, T(s[0]), T(s[1]), s2, dX, dY);
-    if (2LL * ubound > C::S)
+    if (spread > C::S)
         characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
             dm, v, T(s[0]), T(s[1]), s2, dX, dY);
 }
 
 template <class C, bool DOX, bool DOY>
-void char_all_launch(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+void char_all_launch(const Dims& dm, const typename C::T* v, const double* s, int spread,
                      typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
     const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
     characteristics_all_kernel<C, DOX, DOY>
         <<<tile_blocks<C>(dm), kThreads, C::DIM * tile_lds_bytes<C>(), st>>>(dm, v, T(s[0]), T(s[1]),
                                                                           s2, dX, dY);
-    if (2LL * ubound > C::S)
+    if (spread > C::S)
         characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
             dm, v, T(s[0]), T(s[1]), s2, dX, dY);
 }
@@ -689,7 +688,7 @@ void char_all_launch(const Dims& dm, const typename C::T* v, const double* s, in
 constexpr size_t kMaxLds = 160 * 1024;
 
 template <class C>
-void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubound,
+void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int spread,
                typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
     // both directions: all components staged at once (one staging and one
@@ -699,67 +698,72 @@ void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int ubou
     using CA = Tile<T, C::DIM, C::S, 4>;
     if constexpr (C::DIM * tile_lds_bytes<CA>() <= kMaxLds / 2) {
         if (dX && dY) {
-            char_all_launch<CA, true, true>(dm, v, s, ubound, dX, dY, st);
+            char_all_launch<CA, true, true>(dm, v, s, spread, dX, dY, st);
             return;
         }
     }
     // one component staged at a time, one launch per direction in 3-D
     if (C::DIM == 3 || !(dX && dY)) {
-        if (dX) char_launch<C, true, false>(dm, v, s, ubound, dX, dY, st);
-        if (dY) char_launch<C, false, true>(dm, v, s, ubound, dX, dY, st);
+        if (dX) char_launch<C, true, false>(dm, v, s, spread, dX, dY, st);
+        if (dY) char_launch<C, false, true>(dm, v, s, spread, dX, dY, st);
     } else {
-        char_launch<C, true, true>(dm, v, s, ubound, dX, dY, st);
+        char_launch<C, true, true>(dm, v, s, spread, dX, dY, st);
     }
 }
 
 template <class C, int EPI>
 void step_kernels(const Dims& dm, const typename C::T* src, const typename C::T* disp,
-                  const typename C::T* fac, double ht, double sgn, int bound,
+                  const typename C::T* fac, double ht, double sgn, int spread,
                   typename C::T* out, hipStream_t st) {
     using T = typename C::T;
     sl_step_kernel<C, EPI, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
         dm, src, disp, fac, T(ht), T(sgn), out);
-    if (2LL * bound > C::S)
+    if (spread > C::S)
         sl_step_kernel<C, EPI, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
             dm, src, disp, fac, T(ht), T(sgn), out);
 }
 
 template <class C>
 void step_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
-                 const typename C::T* fac, int bound, typename C::T* out, hipStream_t st) {
-    if (fac) step_kernels<C, 1>(dm, src, disp, fac, 0.0, 0.0, bound, out, st);
-    else step_kernels<C, 0>(dm, src, disp, fac, 0.0, 0.0, bound, out, st);
+                 const typename C::T* fac, int spread, typename C::T* out, hipStream_t st) {
+    if (fac) step_kernels<C, 1>(dm, src, disp, fac, 0.0, 0.0, spread, out, st);
+    else step_kernels<C, 0>(dm, src, disp, fac, 0.0, 0.0, spread, out, st);
 }
 
 template <class C>
 void factor_launch(const Dims& dm, const typename C::T* delta, const typename C::T* disp,
-                   double ht, double sgn, int bound, typename C::T* out, hipStream_t st) {
-    step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, bound, out, st);
+                   double ht, double sgn, int spread, typename C::T* out, hipStream_t st) {
+    step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, spread, out, st);
 }
 
-// Calls f(Tile<...>{}) with the variant chosen for `bound`.
+// Calls f(Tile<...>{}) with the variant chosen for `spread`.
 template <typename T, typename F>
-void dispatch_tile(const Dims& dm, int bound, F&& f) {
+void dispatch_tile(const Dims& dm, int spread, F&& f) {
     if (dm.dim == 3) {
-        const int c = pick_capacity<T, 3>(bound);
+        const int c = pick_capacity<T, 3>(spread);
         if (c == 2) f(Tile<T, 3, 2>{});
+        else if (c == 3) f(Tile<T, 3, 3>{});
         else if constexpr (sizeof(T) == 8) f(Tile<T, 3, 4>{});
         else if (c == 4) f(Tile<T, 3, 4>{});
         else f(Tile<T, 3, 8>{});
     } else {
-        if (pick_capacity<T, 2>(bound) == 8) f(Tile<T, 2, 8>{});
+        if (pick_capacity<T, 2>(spread) == 8) f(Tile<T, 2, 8>{});
         else f(Tile<T, 2, 16>{});
     }
 }
 
 }  // namespace
 
+int spread_bound(double B) {
+    if (!(B <= 1.0e6)) return 1 << 21;
+    return static_cast<int>(std::floor(B) + std::ceil(B));
+}
+
 int displacement_bound(double umax, int dim) {
     // |X| = |u(i) + I[u](xi*)| / 2 <= (1 + 1.25^d) max|u| / 2: the cubic
     // Lagrange weights have absolute sum at most 1.25 per axis
-    if (!(umax <= 1.0e6)) return 1 << 20;
-    const double f = 0.5 * (1.0 + std::pow(1.25, dim));
-    return static_cast<int>(std::ceil(f * umax * (1.0 + 1e-6)));
+    if (!(umax <= 1.0e6)) return 1 << 21;
+    return spread_bound(0.5 * (1.0 + std::pow(1.25, dim)) * umax * (1.0 + 1e-6));
 }
 
 template <typename T>
@@ -773,28 +777,28 @@ hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, doub
 }
 
 template <typename T>
-hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int ubound, T* dX,
+hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int spread, T* dX,
                                   T* dY, hipStream_t st) {
-    dispatch_tile<T>(dm, ubound, [&](auto tile) {
-        char_dirs<decltype(tile)>(dm, v, s, ubound, dX, dY, st);
+    dispatch_tile<T>(dm, spread, [&](auto tile) {
+        char_dirs<decltype(tile)>(dm, v, s, spread, dX, dY, st);
     });
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int bound,
+hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int spread,
                           T* out, hipStream_t st) {
-    dispatch_tile<T>(dm, bound, [&](auto tile) {
-        step_launch<decltype(tile)>(dm, src, disp, fac, bound, out, st);
+    dispatch_tile<T>(dm, spread, [&](auto tile) {
+        step_launch<decltype(tile)>(dm, src, disp, fac, spread, out, st);
     });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, int bound, T* out, hipStream_t st) {
-    dispatch_tile<T>(dm, bound, [&](auto tile) {
-        factor_launch<decltype(tile)>(dm, delta, disp, ht, sgn, bound, out, st);
+                                double sgn, int spread, T* out, hipStream_t st) {
+    dispatch_tile<T>(dm, spread, [&](auto tile) {
+        factor_launch<decltype(tile)>(dm, delta, disp, ht, sgn, spread, out, st);
     });
     return hipGetLastError();
 }

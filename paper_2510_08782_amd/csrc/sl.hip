@@ -511,22 +511,37 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
     }
     const Window win = tile_window<C>(fmn, fmx, red);
     if (win.lds != LDS) return;
+    // u at the thread's k-th point (zero outside the grid)
+    auto load_u = [&](int k, T* u, long long& lin, bool& in) {
+        int lx, ly, lz;
+        pm.local(k, lx, ly, lz);
+        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+        in = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+        lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+#pragma unroll
+        for (int q = 0; q < 3; ++q) u[q] = (in && q < DIM) ? v[q * N + lin] * s[q] : T(0);
+    };
     for (int c = 0; c < DIM; ++c) {
         const T* vc = v + c * N;
         if constexpr (LDS) {
             if (c > 0) __syncthreads();
             stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0, win);
         }
+        // the next point's u is loaded while the current one interpolates
+        T un[3];
+        long long linn;
+        bool inn;
+        load_u(0, un, linn, inn);
 #pragma unroll 1
         for (int k = 0; k < C::PTS; ++k) {
+            const T u[3] = {un[0], un[1], un[2]};
+            const long long lin = linn;
+            const bool in = inn;
+            if (k + 1 < C::PTS) load_u(k + 1, un, linn, inn);
+            if (!in) continue;
             int lx, ly, lz;
             pm.local(k, lx, ly, lz);
             const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-            if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
-            const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
-            T u[3];
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) u[q] = v[q * N + lin] * s[q];
             T e0 = T(0), e1, e2;
             if constexpr (DIM == 3) {
                 e0 = u[0];
@@ -602,16 +617,28 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
         else
             stage<C, true>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
     }
-#pragma unroll 1
-    for (int k = 0; k < C::PTS; ++k) {
+    auto load_u = [&](int k, T* u, long long& lin, bool& in) {
         int lx, ly, lz;
         pm.local(k, lx, ly, lz);
         const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
-        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
-        T u[3];
+        in = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+        lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) u[q] = v[q * N + lin] * s[q];
+        for (int q = 0; q < 3; ++q) u[q] = (in && q < DIM) ? v[q * N + lin] * s[q] : T(0);
+    };
+    T un[3];
+    long long linn;
+    bool inn;
+    load_u(0, un, linn, inn);
+#pragma unroll 1
+    for (int k = 0; k < C::PTS; ++k) {
+        const T u[3] = {un[0], un[1], un[2]};
+        const long long lin = linn;
+        const bool in = inn;
+        if (k + 1 < C::PTS) load_u(k + 1, un, linn, inn);
+        if (!in) continue;
+        int lx, ly, lz;
+        pm.local(k, lx, ly, lz);
         const T e0 = DIM == 3 ? u[0] : T(0), e1 = DIM == 3 ? u[1] : u[0];
         const T e2 = DIM == 3 ? u[2] : u[1];
         if (DOX) {

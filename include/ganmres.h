@@ -186,6 +186,21 @@ int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs)
 int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info);
 
+/* Transport map and its Jacobian determinant, the diffeomorphism check shown
+ * with the paper's results (Sec. 3; Sec. 3.5 reports det grad y = 1 for
+ * incompressible flows as min, mean, max and standard deviation).  y is the
+ * foot at t = 0 of the characteristic through x at t = 1, m(1) = m0 o y,
+ * built with the state's semi-Lagrangian steps: y = x + h D,
+ *   D^0 = 0,  D^{j+1}(i) = (X_i - i) + I[D^j](X_i)   (cells, X the RK2
+ * departure points of v), and grad y = Id + (h_a dD_a/dx_b) with spectral
+ * derivatives.  v: device velocity.  det: device image (nullable) receiving
+ * det grad y.  stats: host array of 4 doubles per problem (see
+ * ganmres_batch_count): min, mean, max, standard deviation of det grad y.
+ * The call replaces the handle's departure points, so a following
+ * ganmres_eval_gradient(reuse_forward = 1) needs a new objective evaluation.
+ * Errors: GANMRES_ENONFINITE. */
+int ganmres_deformation(ganmres_handle* h, const void* v, void* det, double* stats);
+
 /* Forget the solver state (k, rho, history); the next ganmres_step starts a
  * new solve from the v it is given. */
 int ganmres_solver_reset(ganmres_handle* h);

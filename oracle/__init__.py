@@ -19,7 +19,10 @@ PDE-constrained optimization problems governed by transport equations":
                 reduced gradient (eq. e:reduced-gradient, e:adjoint).
   ngmres.py     preconditioned fixed-point map with Armijo backtracking
                 (eqs. e:linesearch, e:armijo, e:rpgd, e:fixedpoint), the
-                least-squares mixing step and GA-NGMRES (Alg. 1 and Alg. 3).
+                least-squares mixing step, GA-NGMRES (Alg. 1 and Alg. 3) and
+                GA-AA (Alg. 2 with the alternation of Alg. 3).
+  deformation.py  the transport map y and det grad y reported with the
+                results (Sec. 3, Sec. 3.5).
 
 Every function is written for clarity: full complex FFTs, explicit loops over
 the interpolation stencil, no fusion.  Readings of passages the paper leaves

@@ -79,6 +79,7 @@ def lib():
                                        ctypes.POINTER(vp)]
     L.ganmres_batch_count.argtypes = [vp]
     L.ganmres_batch_values.argtypes = [vp, dp, dp]
+    L.ganmres_deformation.argtypes = [vp, vp, vp, dp]
     L.ganmres_destroy.argtypes = [vp]
     L.ganmres_last_error.argtypes = [vp]
     L.ganmres_last_error.restype = ctypes.c_char_p
@@ -240,6 +241,16 @@ class Problem:
             self._check(lib().ganmres_timing_get(self.h, kidx, ctypes.byref(ms), ctypes.byref(cnt)))
             out[lib().ganmres_kernel_name(kidx).decode()] = (ms.value, cnt.value)
         return out
+
+    def deformation(self, v, want_det=True):
+        """det grad y of the transport map of v: (det image or None, list of
+        (min, mean, max, std) per problem)."""
+        n = lib().ganmres_batch_count(self.h)
+        det = self.torch.empty(self.shape, dtype=self.dtype, device=self.m0.device) if want_det else None
+        st = (ctypes.c_double * (4 * n))()
+        self._check(lib().ganmres_deformation(self.h, self._vec(v).data_ptr(),
+                                              det.data_ptr() if want_det else None, st))
+        return det, [tuple(st[4 * i:4 * i + 4]) for i in range(n)]
 
     def values(self):
         """Per-problem J and mismatch of the last evaluation (lists)."""

@@ -29,6 +29,10 @@ hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, i
 template <typename T>
 hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int spread,
                           T* out, hipStream_t st);
+// out = add + I[src](i + disp)   (one step of the deformation map)
+template <typename T>
+hipError_t launch_sl_step_add(const Dims& dm, const T* src, const T* disp, const T* add,
+                              int spread, T* out, hipStream_t st);
 // out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
@@ -77,6 +81,14 @@ hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Se
 template <typename T>
 hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int K, T* out,
                           const Seg& g, hipStream_t st);
+
+// det grad y per point, y = x + h D, from J[a d + b] = dD_a/dx_b (d = 2, 3;
+// h[a]: cell size along component a's axis).  det (nullable) receives the
+// field; per segment s: res[s] = -min, res[nseg + s] = max,
+// res[2 nseg + s] = sum (det - 1), res[3 nseg + s] = sum (det - 1)^2.
+template <typename T>
+hipError_t launch_det_stats(const T* const* J, const double* h, int d, const Seg& g, T* det,
+                            double* partial, double* res, hipStream_t st);
 
 // ---- spectral kernels (spectral.hip) ----------------------------------------
 template <typename T>

@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(1024) finish_kernel(const double* __restrict__
                                                       int nq, double* __restrict__ res) {
     __shared__ double sh[1024 / 64];
     for (int q = 0; q < nq; ++q) {
-        double x = 0.0;
+        double x = MAX ? -INFINITY : 0.0;
         for (int i = threadIdx.x; i < nb; i += blockDim.x)
             x = MAX ? fmax(x, partial[(long long)q * nb + i]) : x + partial[(long long)q * nb + i];
         const double r = block_reduce<MAX>(x, sh);

@@ -193,6 +193,7 @@ class ProblemBase {
     // info: one entry per stacked problem
     virtual void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) = 0;
     virtual int count() const = 0;
+    virtual void deformation(const void* v, void* det, double* stats) = 0;
     virtual void values(double* J, double* mismatch) const = 0;
     virtual void reset() = 0;
     virtual void get_field(int which, int j, void* out) = 0;
@@ -830,6 +831,68 @@ class Problem : public ProblemBase {
     }
 
     int count() const override { return nb; }
+
+    // Deformation map y = x + h D (D^0 = 0, D^{j+1} = (X - i) + I[D^j](X)) and
+    // det grad y with its (min, mean, max, std) per problem; det: device image
+    // (nullable).  Uses the state's departure points of v.
+    std::vector<std::unique_ptr<DevBuf>> dfm_bufs;
+    void deformation(const void* v, void* det, double* stats) override {
+        prepare(v, false);
+        // dX now belongs to v: a kept forward history of another velocity is void
+        fwd_valid = false;
+        adj_valid = false;
+        y_valid = false;
+        if (dfm_bufs.empty()) {
+            for (int i = 0; i < 2 + d * d; ++i) {
+                dfm_bufs.emplace_back(new DevBuf);
+                dfm_bufs.back()->alloc(sizeof(T) * (i < 2 ? d * N : N));
+            }
+        }
+        T* Da = static_cast<T*>(dfm_bufs[0]->p);
+        T* Db = static_cast<T*>(dfm_bufs[1]->p);
+        // D^1 = X - i
+        HIPCHK(hipMemcpyAsync(Da, dX, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        for (int j = 1; j < cfg.nt; ++j) {
+            for (int a = 0; a < d; ++a)
+                run(KC_SL, [&] {
+                    return launch_sl_step_add<T>(dm, comp(Da, a), dX, comp(dX, a), dbound,
+                                                 comp(Db, a), st);
+                });
+            std::swap(Da, Db);
+        }
+        // J[a d + b] = dD_a / dx_b
+        std::vector<const T*> J(d * d);
+        const double one = 1.0;
+        for (int a = 0; a < d; ++a)
+            for (int bb = 0; bb < d; ++bb) {
+                T* out = static_cast<T*>(dfm_bufs[2 + a * d + bb]->p);
+                const T* f = comp(Da, a);
+                run(KC_DERIV, [&] {
+                    return launch_deriv_axis<T>(dm, plans, comp_axis(d, bb), &f, nullptr, &one, 1,
+                                                0, out, st);
+                });
+                J[a * d + bb] = out;
+            }
+        double hc[3];
+        for (int a = 0; a < d; ++a) hc[a] = h[comp_axis(d, a)];
+        run(KC_REDUCE, [&] {
+            return launch_det_stats<T>(J.data(), hc, d, sseg(), static_cast<T*>(det), partial,
+                                       dres + R_GRAM, st);
+        });
+        const double* r = fetch(R_GRAM, 4 * nb);
+        bool finite = true;
+        for (int i = 0; i < nb; ++i) {
+            const double mn = -r[i], mx = r[nb + i];
+            const double m1 = r[2 * nb + i] / double(Nt), m2 = r[3 * nb + i] / double(Nt);
+            const double var = std::max(0.0, m2 - m1 * m1);
+            stats[4 * i + 0] = mn;
+            stats[4 * i + 1] = 1.0 + m1;
+            stats[4 * i + 2] = mx;
+            stats[4 * i + 3] = std::sqrt(var);
+            finite = finite && std::isfinite(mn) && std::isfinite(mx) && std::isfinite(m1);
+        }
+        if (!finite) throw Error(GANMRES_ENONFINITE, "non-finite deformation gradient");
+    }
     void values(double* J, double* mis) const override {
         for (int i = 0; i < nb; ++i) {
             if (J) J[i] = J_s[i];
@@ -1337,6 +1400,14 @@ int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
             h->impl->step(*p, v, info);
         }
     });
+}
+
+int ganmres_deformation(ganmres_handle* h, const void* v, void* det, double* stats) {
+    if (!h || !v || !stats) {
+        if (h) h->err = "invalid arguments";
+        return GANMRES_EINVAL;
+    }
+    return guarded(h, [&] { h->impl->deformation(v, det, stats); });
 }
 
 int ganmres_solver_reset(ganmres_handle* h) {

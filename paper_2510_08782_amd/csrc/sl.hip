@@ -388,10 +388,13 @@ int tile_blocks(const Dims& dm) {
 }
 
 // ---- semi-Lagrangian step --------------------------------------------------------
+// r = I[src] at the point; EPI 0: out = r;  1: out = fac r;  3: out = fac + r;
+// 2 (source factor, src = delta): out = 1 + sgn h/2 (r + delta) + h^2/2 delta r
 template <typename T, int EPI>
 __device__ inline T step_epilogue(T r, const T* __restrict__ src, const T* __restrict__ fac,
                                   long long lin, T ht, T sgn) {
     if constexpr (EPI == 1) r *= fac[lin];
+    if constexpr (EPI == 3) r += fac[lin];
     if constexpr (EPI == 2) {
         const T dc = src[lin];
         r = T(1) + sgn * T(0.5) * ht * (r + dc) + T(0.5) * ht * ht * dc * r;
@@ -758,6 +761,12 @@ void step_launch(const Dims& dm, const typename C::T* src, const typename C::T* 
 }
 
 template <class C>
+void add_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
+                const typename C::T* add, int spread, typename C::T* out, hipStream_t st) {
+    step_kernels<C, 3>(dm, src, disp, add, 0.0, 0.0, spread, out, st);
+}
+
+template <class C>
 void factor_launch(const Dims& dm, const typename C::T* delta, const typename C::T* disp,
                    double ht, double sgn, int spread, typename C::T* out, hipStream_t st) {
     step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, spread, out, st);
@@ -822,6 +831,15 @@ hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* 
 }
 
 template <typename T>
+hipError_t launch_sl_step_add(const Dims& dm, const T* src, const T* disp, const T* add,
+                              int spread, T* out, hipStream_t st) {
+    dispatch_tile<T>(dm, spread, [&](auto tile) {
+        add_launch<decltype(tile)>(dm, src, disp, add, spread, out, st);
+    });
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
                                 double sgn, int spread, T* out, hipStream_t st) {
     dispatch_tile<T>(dm, spread, [&](auto tile) {
@@ -837,6 +855,8 @@ hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, d
                                                   T*, hipStream_t);                               \
     template hipError_t launch_sl_step<T>(const Dims&, const T*, const T*, const T*, int, T*,     \
                                           hipStream_t);                                           \
+    template hipError_t launch_sl_step_add<T>(const Dims&, const T*, const T*, const T*, int, T*, \
+                                              hipStream_t);                                       \
     template hipError_t launch_source_factor<T>(const Dims&, const T*, const T*, double, double,  \
                                                 int, T*, hipStream_t);
 GAN_INST(float)

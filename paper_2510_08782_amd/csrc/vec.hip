@@ -154,6 +154,57 @@ __global__ void combine_kernel(const T* __restrict__ q, CombineArgs<T> ca,
     }
 }
 
+// det of grad y = Id + (h_a dD_a/dx_b) from the d x d derivative fields
+// J[a d + b] = dD_a/dx_b; per segment: max(-det), max(det), sum(det - 1),
+// sum((det - 1)^2) (NaN counts as -inf / +inf for the extremes).
+template <typename T>
+struct DetArgs {
+    const T* J[9];
+    double h[3];
+    int d;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) det_stats_kernel(DetArgs<T> a, Seg g, T* det,
+                                                                double* __restrict__ partial) {
+    __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
+    double mn = -INFINITY, mx = -INFINITY, s1 = 0.0, s2 = 0.0;
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long e = s * g.seglen + i;
+        double m[3][3];
+        for (int r = 0; r < a.d; ++r)
+            for (int c = 0; c < a.d; ++c)
+                m[r][c] = (r == c ? 1.0 : 0.0) + a.h[r] * static_cast<double>(a.J[r * a.d + c][e]);
+        const double dt = a.d == 2 ? m[0][0] * m[1][1] - m[0][1] * m[1][0]
+                                   : m[0][0] * (m[1][1] * m[2][2] - m[1][2] * m[2][1]) -
+                                         m[0][1] * (m[1][0] * m[2][2] - m[1][2] * m[2][0]) +
+                                         m[0][2] * (m[1][0] * m[2][1] - m[1][1] * m[2][0]);
+        if (det) det[e] = static_cast<T>(dt);
+        if (dt == dt) {
+            mn = fmax(mn, -dt);
+            mx = fmax(mx, dt);
+            s1 += dt - 1.0;
+            s2 += (dt - 1.0) * (dt - 1.0);
+        } else {
+            mn = mx = INFINITY;
+            s1 = s2 = NAN;
+        }
+    }
+    const double r0 = block_reduce<true>(mn, sh);
+    const double r1 = block_reduce<true>(mx, sh);
+    const double r2 = block_reduce<false>(s1, sh);
+    const double r3 = block_reduce<false>(s2, sh);
+    if (threadIdx.x == 0) {
+        const long long nb = gridDim.x, ns = gridDim.y;
+        partial[(0 * ns + s) * nb + blockIdx.x] = r0;
+        partial[(1 * ns + s) * nb + blockIdx.x] = r1;
+        partial[(2 * ns + s) * nb + blockIdx.x] = r2;
+        partial[(3 * ns + s) * nb + blockIdx.x] = r3;
+    }
+}
+
 inline int stream_blocks(long long n) {
     long long b = (n + 255) / 256;
     if (b > 8192) b = 8192;
@@ -251,6 +302,22 @@ hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partia
 }
 
 template <typename T>
+hipError_t launch_det_stats(const T* const* J, const double* h, int d, const Seg& g, T* det,
+                            double* partial, double* res, hipStream_t st) {
+    if (!seg_valid(g) || (d != 2 && d != 3)) return hipErrorInvalidValue;
+    DetArgs<T> a{};
+    for (int q = 0; q < d * d; ++q) a.J[q] = J[q];
+    for (int q = 0; q < 3; ++q) a.h[q] = q < d ? h[q] : 0.0;
+    a.d = d;
+    const int nb = seg_blocks(g, 4);
+    det_stats_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, det, partial);
+    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 2 * g.nseg, res);
+    finish_kernel<false><<<1, 1024, 0, st>>>(partial + (long long)2 * g.nseg * nb, nb, 2 * g.nseg,
+                                             res + 2 * g.nseg);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Seg& g,
                        hipStream_t st) {
     if (!seg_valid(g)) return hipErrorInvalidValue;
@@ -282,7 +349,9 @@ hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int
     template hipError_t launch_axpy<T>(const T*, const double*, const T*, T*, const Seg&,         \
                                        hipStream_t);                                              \
     template hipError_t launch_combine<T>(const T*, const T* const*, const double*, int, T*,      \
-                                          const Seg&, hipStream_t);
+                                          const Seg&, hipStream_t);                               \
+    template hipError_t launch_det_stats<T>(const T* const*, const double*, int, const Seg&, T*,  \
+                                            double*, double*, hipStream_t);
 GAN_INST(float)
 GAN_INST(double)
 #undef GAN_INST

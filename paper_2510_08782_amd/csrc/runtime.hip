@@ -622,6 +622,15 @@ class Problem : public ProblemBase {
         const int n = reg_from_device ? R_REG + nb : nb;
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
+        return J_from_host(mis_out);
+    }
+    // copy the ingredients of J to the host behind an event (see J_from_host)
+    void J_to_host() {
+        const int n = reg_from_device ? R_REG + nb : nb;
+        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipEventRecord(ev_res, st));
+    }
+    double J_from_host(double* mis_out) {
         double Jt = 0.0, mt = 0.0;
         for (int i = 0; i < nb; ++i) {
             mis_s[i] = 0.5 * cell * hres[R_MIS + i];
@@ -739,19 +748,17 @@ class Problem : public ProblemBase {
     }
 
     double gradient(const void* v, void* g, bool reuse) override {
-        double J;
         if (reuse) {
             if (!fwd_valid || fwd_v != v)
                 throw Error(GANMRES_ESTATE, "reuse_forward without a kept forward solve for this v");
             ensure_Y(v);
-            mismatch(true);
-            J = finish_J(nullptr);
         } else {
             prepare(v, true);
             forward();
-            mismatch(true);
-            J = finish_J(nullptr);
         }
+        mismatch(true);
+        // J reaches the host while the adjoint and the assembly run
+        J_to_host();
         backward();
         // assembly g = alpha L v + [P] b
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
@@ -761,7 +768,8 @@ class Problem : public ProblemBase {
         });
         T* gout[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / Nt, d, st); });
-        return J;
+        HIPCHK(hipEventSynchronize(ev_res));
+        return J_from_host(nullptr);
     }
 
     double precond(const void* g, void* s) override {

@@ -662,18 +662,25 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
 // max_c max_i |s_c v_c(i)| (NaN/inf counted as 1e30): FP64 block partials
 template <typename T>
 __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restrict__ v,
-                                                                long long N, int dim, T s0, T s1,
-                                                                T s2, double* __restrict__ partial) {
+                                                                long long N, int dim, double s0,
+                                                                double s1, double s2,
+                                                                double* __restrict__ partial) {
     __shared__ double sh[kThreads / 64];
-    const T s[3] = {s0, s1, s2};
+    const double s[3] = {s0, s1, s2};
     double m = 0.0;
-    for (int c = 0; c < dim; ++c)
+    bool bad = false;
+    for (int c = 0; c < dim; ++c) {
+        // max |v_c| in the field's type, scaled once (s_c > 0)
+        T mc = T(0);
         for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
              i += (long long)gridDim.x * blockDim.x) {
-            double a = fabs(double(v[c * N + i]) * double(s[c]));
-            if (!(a <= 1.0e30)) a = 1.0e30;
-            m = fmax(m, a);
+            const T a = fabs(v[c * N + i]);
+            bad = bad || !(a == a);
+            mc = fmax(mc, a);
         }
+        m = fmax(m, double(mc) * s[c]);
+    }
+    if (bad || !(m <= 1.0e30)) m = 1.0e30;
     const double r = block_reduce<true>(m, sh);
     if (threadIdx.x == 0) partial[blockIdx.x] = r;
 }
@@ -806,8 +813,8 @@ template <typename T>
 hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, double* partial,
                                double* res, hipStream_t st) {
     const int nb = reduction_blocks(dm.N);
-    velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, T(s[0]), T(s[1]),
-                                                    T(dm.dim == 3 ? s[2] : 0.0), partial);
+    velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, s[0], s[1],
+                                                    dm.dim == 3 ? s[2] : 0.0, partial);
     finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 1, res);
     return hipGetLastError();
 }

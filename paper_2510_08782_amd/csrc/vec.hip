@@ -70,15 +70,17 @@ __global__ void __launch_bounds__(kRedThreads) maxabs_kernel(const T* __restrict
                                                              double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
     const int s = blockIdx.y;
-    double m = 0.0;
+    T m = T(0);
+    bool bad = false;
     for (int c = 0; c < g.ncomp; ++c)
         for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
              i += (long long)gridDim.x * blockDim.x) {
-            double x = fabs(static_cast<double>(a[seg_at(g, c, s, i)]));
-            if (!(x <= 1.0e308)) x = INFINITY;  // NaN and inf both count as inf
+            const T x = fabs(a[seg_at(g, c, s, i)]);
+            bad = bad || !(x == x);
             m = fmax(m, x);
         }
-    const double r = block_reduce<true>(m, sh);
+    // NaN and inf both count as inf
+    const double r = block_reduce<true>(bad ? INFINITY : static_cast<double>(m), sh);
     if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
 }
 

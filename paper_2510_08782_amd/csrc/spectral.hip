@@ -31,6 +31,7 @@ constexpr int kFftThreads = 256;
 constexpr int kItems = 8;           // tile elements per thread (tile <= 2048 elements)
 constexpr int kMaxTime = 65;
 constexpr int kLdsBudget = 64 * 1024;
+constexpr int kTilesPerBlock = 2;  // grid-strided transforms: tiles per workgroup
 
 // log2 of the complex pencils per tile for kernels whose tile holds 2 PC real
 // pencils of length L (2 PC L <= kFftThreads * kItems), with two complex LDS
@@ -285,30 +286,58 @@ __global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<
     const int nh = dm.n2h;
     const long long npen = pencil_count(dm, axis, nh);
     const long long stride = pencil_stride(dm, axis, nh);
-    const long long p0 = (long long)blockIdx.x << pcshift;
+    const long long ntiles = (npen + PC - 1) >> pcshift;
     const int pl_ = threadIdx.x & (PC - 1);
-    const bool ok = p0 + pl_ < npen;
-    const long long base = ok ? pencil_base(dm, axis, nh, p0 + pl_) : 0;
     const int nitems = PC * L;
+    // Tiles of PC adjacent pencils, grid-strided over the workgroups; the next
+    // tile's data is loaded into registers while the current one transforms.
+    auto load = [&](long long tile, C2<T>* vals, long long& base, bool& ok) {
+        const long long p = (tile << pcshift) + pl_;
+        ok = p < npen;
+        base = ok ? pencil_base(dm, axis, nh, p) : 0;
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            vals[e] = (q < nitems && ok) ? spec[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+        }
+    };
+    long long tile = blockIdx.x;
+    if (tile >= ntiles) return;
     C2<T> vals[kItems];
+    long long base;
+    bool ok;
+    load(tile, vals, base, ok);
+    for (;;) {
 #pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        const int i = q >> pcshift;
-        vals[e] = (q < nitems && ok) ? spec[base + i * stride] : cmk(T(0), T(0));
-    }
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            if (q < nitems) bufA[lpad(q)] = vals[e];
+        }
+        __syncthreads();
+        const long long next = tile + gridDim.x;
+        long long nbase = 0;
+        bool nok = false;
+        if (next < ntiles) load(next, vals, nbase, nok);
+        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
 #pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        if (q < nitems) bufA[lpad(q)] = vals[e];
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
+        }
+        if (next >= ntiles) break;
+        __syncthreads();  // every thread has read Z before bufA is refilled
+        tile = next;
+        base = nbase;
+        ok = nok;
     }
-    __syncthreads();
-    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
-#pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
-    }
+}
+
+// Workgroups for a grid-strided transform of `tiles` tiles per field: about
+// `per` tiles each, so that the prefetch of the next tile has a tile to
+// overlap with.
+inline unsigned strided_blocks(long long tiles, int per) {
+    long long b = (tiles + per - 1) / per;
+    return (unsigned)(b < 1 ? 1 : b);
 }
 
 // Half-spectrum rows -> real rows: out = scale * x [+ add].
@@ -624,7 +653,7 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const long long npen = pencil_count(dm, axis, dm.n2h);
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen);
         const int PC = 1 << sh;
-        dim3 g((unsigned)((npen + PC - 1) / PC), count);
+        dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         with_length(L, [&](auto lc) {
             c2c_axis_kernel<TC, decltype(lc)::value>
                 <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[axis], axis,
@@ -651,7 +680,7 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const long long npen = pencil_count(dm, axis, dm.n2h);
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
         const int PC = 1 << sh;
-        dim3 g((unsigned)((npen + PC - 1) / PC), count);
+        dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         with_length(L, [&](auto lc) {
             c2c_axis_kernel<T, decltype(lc)::value>
                 <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(dm, pl.p[axis], axis,

@@ -55,8 +55,8 @@ enum {
 enum { GANMRES_ADVECTION = 0, GANMRES_CONTINUITY = 1 };
 enum { GANMRES_F32 = 0, GANMRES_F64 = 1 };
 enum { GANMRES_VARIANT_GA = 0, GANMRES_VARIANT_ALT = 1 };
-enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1, GANMRES_STEP_AA = 2 };
-enum { GANMRES_ACCEL_NGMRES = 0, GANMRES_ACCEL_AA = 1 };
+enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1, GANMRES_STEP_AA = 2, GANMRES_STEP_NEWTON = 3 };
+enum { GANMRES_ACCEL_NGMRES = 0, GANMRES_ACCEL_AA = 1, GANMRES_ACCEL_NK = 2 };
 
 typedef struct ganmres_handle ganmres_handle;
 
@@ -84,20 +84,23 @@ typedef struct {
     double rho_cap;        /* cap on the stored step, <= 0 means none           */
     int variant;           /* GANMRES_VARIANT_GA: FP when mod(k,s+t) >= sigma;
                               GANMRES_VARIANT_ALT: FP when mod(k,s+t) < tau     */
-    int accel;             /* GANMRES_ACCEL_NGMRES (Alg. 1/3) or GANMRES_ACCEL_AA
+    int accel;             /* GANMRES_ACCEL_NGMRES (Alg. 1/3), GANMRES_ACCEL_AA
                               (Anderson acceleration, Alg. 2, with the same
-                              alternation: GA-AA)                               */
+                              alternation: GA-AA) or GANMRES_ACCEL_NK (the
+                              Gauss-Newton-Krylov baseline, Appendix A; w,
+                              sigma, tau, variant and rho_cap unused)           */
 } ganmres_solver_params;
 
 #define GANMRES_MAX_WINDOW 64
 
 typedef struct {
     int k;                 /* iterations completed after this call              */
-    int step_kind;         /* GANMRES_STEP_NGMRES, GANMRES_STEP_AA or _FP       */
+    int step_kind;         /* GANMRES_STEP_NGMRES, _AA, _FP or _NEWTON          */
     int stop;              /* 1 when the stopping rule of Alg. 3 holds          */
     int n_trials;          /* objective evaluations in this line search         */
     int n_grad;            /* gradient evaluations in this call                 */
-    int n_beta;            /* number of valid entries in beta                   */
+    int n_beta;            /* number of valid entries in beta (Newton steps:
+                              the CG iterations taken)                          */
     double J;              /* J(v^{k+1})                                        */
     double J_q;            /* J(q(v^k))                                         */
     double ginf;           /* ||g(v^{k+1})||_inf                                */
@@ -180,9 +183,16 @@ int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs)
  * rho, the window (the last w+1 pairs (v, g), or the last w pairs
  * (v - q(v), q(v)) for AA) and ||g(v^0)||_inf.  info: host array of
  * ganmres_batch_count(h) entries (one per problem), nullable.
+ * With accel = GANMRES_ACCEL_NK the call is one inexact Gauss-Newton-Krylov
+ * iteration instead (Appendix A): preconditioned CG on H_gn s = -g (see
+ * ganmres_hessian_matvec) with the preconditioner (alpha L_p)^-1, stopped when
+ * ||r||_h <= min(1/2, sqrt(||g||_h / ||g(v^0)||_h)) ||g||_h or after 50
+ * iterations, then Armijo backtracking from rho = 1 (advection model, full
+ * history, single problem).
  * Errors: GANMRES_EINVAL (w < 0 or > GANMRES_MAX_WINDOW, sigma = tau = 0,
- * negative counts, unknown accel, accel or w changed without a reset),
- * GANMRES_ELINESEARCH, GANMRES_ELSQ, GANMRES_ENONFINITE. */
+ * negative counts, unknown accel, accel or w changed without a reset,
+ * GANMRES_ACCEL_NK outside its setting), GANMRES_ELINESEARCH, GANMRES_ELSQ,
+ * GANMRES_ENONFINITE. */
 int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info);
 
@@ -200,6 +210,19 @@ int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
  * ganmres_eval_gradient(reuse_forward = 1) needs a new objective evaluation.
  * Errors: GANMRES_ENONFINITE. */
 int ganmres_deformation(ganmres_handle* h, const void* v, void* det, double* stats);
+
+/* Gauss-Newton Hessian matvec of the Newton-Krylov baseline (Appendix A,
+ * eqs. e:hessian-matvec, e:incremental-state, e:incremental-adjoint with the
+ * terms carrying lam dropped):
+ *   out = H_gn[v] vt = alpha L_p vt + [P] int lt grad m dt,
+ * with the incremental state mt (mt(0) = 0, source -vt . grad m) integrated
+ * along the state's characteristics by the trapezoidal rule, and lt solving
+ * the adjoint equation with final value -mt(1).  v, vt, out: device
+ * velocities; out may alias neither.  The state of v is solved again on every
+ * call.  The advection model with the full state history on a single
+ * problem only.  The call replaces the handle's adjoint fields.
+ * Errors: GANMRES_EINVAL (continuity model, checkpoint_every > 1, a batch). */
+int ganmres_hessian_matvec(ganmres_handle* h, const void* v, const void* vt, void* out);
 
 /* Forget the solver state (k, rho, history); the next ganmres_step starts a
  * new solve from the v it is given. */

@@ -23,8 +23,8 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "ganmres.h")
 ADVECTION, CONTINUITY = 0, 1
 F32, F64 = 0, 1
 VARIANT_GA, VARIANT_ALT = 0, 1
-STEP_NGMRES, STEP_FP, STEP_AA = 0, 1, 2
-ACCEL_NGMRES, ACCEL_AA = 0, 1
+STEP_NGMRES, STEP_FP, STEP_AA, STEP_NEWTON = 0, 1, 2, 3
+ACCEL_NGMRES, ACCEL_AA, ACCEL_NK = 0, 1, 2
 MAX_WINDOW = 64
 
 ERRORS = {
@@ -80,6 +80,7 @@ def lib():
     L.ganmres_batch_count.argtypes = [vp]
     L.ganmres_batch_values.argtypes = [vp, dp, dp]
     L.ganmres_deformation.argtypes = [vp, vp, vp, dp]
+    L.ganmres_hessian_matvec.argtypes = [vp, vp, vp, vp]
     L.ganmres_destroy.argtypes = [vp]
     L.ganmres_last_error.argtypes = [vp]
     L.ganmres_last_error.restype = ctypes.c_char_p
@@ -215,6 +216,13 @@ class Problem:
                                        ctypes.byref(info)))
         return info
 
+    def hessian_matvec(self, v, vt, out=None):
+        """Gauss-Newton Hessian H_gn[v] applied to vt (the Newton-Krylov baseline)."""
+        out = self.new_velocity() if out is None else self._vec(out)
+        self._check(lib().ganmres_hessian_matvec(self.h, self._vec(v).data_ptr(),
+                                                 self._vec(vt).data_ptr(), out.data_ptr()))
+        return out
+
     def reset(self):
         self._check(lib().ganmres_solver_reset(self.h))
 
@@ -260,8 +268,9 @@ class Problem:
         return list(J), list(mis)
 
     def solve(self, params: SolveParams, v0=None, callback=None):
-        """Run GA-NGMRES, or GA-AA when params.accel is ACCEL_AA, from v0
-        (default 0) until the stopping rule holds."""
+        """Run GA-NGMRES, GA-AA when params.accel is ACCEL_AA, or the
+        Gauss-Newton-Krylov baseline when it is ACCEL_NK, from v0 (default 0)
+        until the stopping rule holds."""
         v = self.new_velocity() if v0 is None else self._vec(v0).clone()
         self.reset()
         infos = []

@@ -194,6 +194,7 @@ class ProblemBase {
     virtual void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) = 0;
     virtual int count() const = 0;
     virtual void deformation(const void* v, void* det, double* stats) = 0;
+    virtual void hessian_matvec(const void* v, const void* vt, void* out) = 0;
     virtual void values(double* J, double* mismatch) const = 0;
     virtual void reset() = 0;
     virtual void get_field(int which, int j, void* out) = 0;
@@ -755,6 +756,8 @@ class Problem : public ProblemBase {
         } else {
             prepare(v, true);
             forward();
+            fwd_valid = true;
+            fwd_v = v;
         }
         mismatch(true);
         // J reaches the host while the adjoint and the assembly run
@@ -836,6 +839,215 @@ class Problem : public ProblemBase {
         }
         HIPCHK(hipMemcpyAsync(out, src, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+    }
+
+    // ---- Gauss-Newton-Krylov baseline (Appendix A) ---------------------------
+    // Gauss-Newton Hessian matvec H_gn[v] vt = alpha L vt + [P] int lt grad m dt
+    // (eqs. e:hessian-matvec, e:incremental-state, e:incremental-adjoint, the
+    // terms carrying lam dropped): the incremental state is integrated along
+    // the state's characteristics with the trapezoidal rule for its source
+    // f = -vt . grad m, the Gauss-Newton adjoint with the adjoint's scheme and
+    // final value -mt(1).  With g^j = mt^j + h_t/2 f^j the state step is one
+    // gather, g^{j+1} = I[g^j](X) + h_t f^{j+1}; the adjoint is carried as
+    // L^j = -lt^j (linear), so the body force takes the weights -w_j.
+    std::vector<std::unique_ptr<DevBuf>> nk_bufs;  // sources (nt+1) N, g ping-pong 2 N
+    C2<double>* vth[3] = {nullptr, nullptr, nullptr};
+    void ensure_matvec_buffers() {
+        if (!nk_bufs.empty()) return;
+        auto add = [&](size_t bytes) {
+            nk_bufs.emplace_back(new DevBuf);
+            nk_bufs.back()->alloc(bytes);
+            ws_bytes += (long long)bytes;
+            return nk_bufs.back()->p;
+        };
+        add(sizeof(T) * (cfg.nt + 1) * N);
+        for (int i = 0; i < 2; ++i) add(sizeof(T) * N);
+        for (int c = 0; c < d; ++c) vth[c] = static_cast<C2<double>*>(add(sizeof(C2<double>) * NH));
+    }
+
+    void check_newton_setup() const {
+        if (cfg.model != GANMRES_ADVECTION || !full || nb != 1)
+            throw Error(GANMRES_EINVAL,
+                        "the Gauss-Newton Hessian needs the advection model, the full state history "
+                        "(checkpoint_every = 1) and a single problem");
+    }
+
+    // the caller's v may have changed since any earlier call: solve the state again
+    void hessian_matvec(const void* v, const void* vt, void* out) override {
+        check_newton_setup();
+        prepare(v, true);
+        forward();
+        fwd_valid = true;
+        fwd_v = v;
+        gn_matvec(v, vt, out);
+    }
+
+    // H_gn[v] vt with the state history, departure points and adjoint factors of
+    // v current
+    void gn_matvec(const void* v, const void* vt, void* out) {
+        ensure_matvec_buffers();
+        ensure_Y(v);
+        adj_valid = false;  // lamh is about to hold the incremental adjoint
+        const int nt = cfg.nt;
+        T* f = static_cast<T*>(nk_bufs[0]->p);  // h_t f^j = -h_t vt . grad m^j
+        T* ga = static_cast<T*>(nk_bufs[1]->p);
+        T* gb = static_cast<T*>(nk_bufs[2]->p);
+        const double wsrc = -ht;
+        for (int j = 0; j <= nt; ++j) {
+            const T* mj = mstate(j);
+            for (int c = 0; c < d; ++c) {
+                const T* vc = comp(vt, c);
+                run(KC_DERIV, [&] {
+                    return launch_deriv_axis<T>(dm, plans, comp_axis(d, c), &mj, &vc, &wsrc, 1,
+                                                c > 0, f + (long long)j * N, st);
+                });
+            }
+        }
+        const std::vector<double> mhalf(1, -0.5);
+        // g^0 = h_t f^0 / 2
+        run(KC_VEC, [&] { return launch_axpy<T>(f, mhalf.data(), f, ga, sseg(), st); });
+        for (int j = 0; j < nt; ++j) {
+            run(KC_SL, [&] {
+                return launch_sl_step_add<T>(dm, ga, dX, f + (long long)(j + 1) * N, dbound, gb, st);
+            });
+            std::swap(ga, gb);
+        }
+        // L^nt = mt^nt = g^nt - h_t f^nt / 2, then L^j = [c_b] I[L^{j+1}](Y)
+        run(KC_VEC, [&] {
+            return launch_axpy<T>(ga, mhalf.data(), f + (long long)nt * N, lamh + (long long)nt * N,
+                                  sseg(), st);
+        });
+        for (int j = nt - 1; j >= 0; --j)
+            run(KC_SL, [&] {
+                return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
+                                         lamh + (long long)j * N, st);
+            });
+        std::vector<const T*> mp(nt + 1), lp(nt + 1);
+        std::vector<double> w(nt + 1);
+        for (int t = 0; t <= nt; ++t) {
+            mp[t] = mhist + (long long)t * N;
+            lp[t] = lamh + (long long)t * N;
+            w[t] = -trap_weight(t);
+        }
+        body_force(mp, lp, w, false);
+        // assembly: alpha L vt + [P] b (FP64 spectrum of vt, as for v)
+        const T* vin[3] = {comp(vt, 0), comp(vt, 1), d == 3 ? comp(vt, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vth, d, st); });
+        const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
+        run(KC_SPEC, [&] {
+            return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vth, wh, wh, st);
+        });
+        T* hout[3] = {comp(out, 0), comp(out, 1), d == 3 ? comp(out, 2) : nullptr};
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, hout, nullptr, 1.0 / Nt, d, st); });
+    }
+
+    // <a, b>_h (FP64; single problem)
+    double inner(const T* a, const T* bb) {
+        run(KC_REDUCE, [&] { return launch_dot<T>(a, bb, vseg(), partial, dres + R_DOT, st); });
+        return cell * fetch(R_DOT, 1)[0];
+    }
+
+    // One iteration of the inexact Gauss-Newton-Krylov method: PCG on
+    // H_gn s = -g with the regulariser preconditioner ("ireg") to the forcing
+    // tolerance min(1/2, sqrt(||g|| / ||g_0||)) (at most kCgMaxit
+    // iterations), then Armijo backtracking from rho = 1.
+    static constexpr int kCgMaxit = 50;
+    double nk_g0norm = 0.0;
+    void step_nk(const ganmres_solver_params& p, void* v, ganmres_step_info* info) {
+        check_newton_setup();
+        int ngrad = 0;
+        T* V = rv(0);
+        T* G = rg(0);
+        if (!started) {
+            start(p, v, V, G, ngrad);
+            nk_g0norm = std::sqrt(inner(G, G));
+        }
+        T* S = rv(1);  // CG iterate, then the step
+        T* Q = rg(1);  // -r
+        T* Z = static_cast<T*>(gqb->p);
+        T* Pd = static_cast<T*>(aa_r[0]->p);
+        T* HP = static_cast<T*>(aa_q[0]->p);
+        const double gn = std::sqrt(inner(G, G));
+        const double tol = std::min(0.5, std::sqrt(gn / nk_g0norm));
+        // CG from x = 0 on H x = b = -g.  Q holds -r (Q = g at the start), the
+        // preconditioner gives Z = -(alpha L)^-1 Q = M^-1 r and <r, z> = -<Q, Z>;
+        // the state history of V stays current through the iteration
+        HIPCHK(hipMemsetAsync(S, 0, sizeof(T) * d * N, st));
+        HIPCHK(hipMemcpyAsync(Q, G, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        precond_keep(Q, Z, false);
+        HIPCHK(hipMemcpyAsync(Pd, Z, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        double rz = -gs_s[0];
+        int its = 0;
+        for (int it = 1; it <= kCgMaxit; ++it) {
+            gn_matvec(V, Pd, HP);
+            const double pHp = inner(Pd, HP);
+            if (!(pHp > 0.0)) break;
+            const double a = rz / pHp;
+            const std::vector<double> av(1, a);
+            run(KC_VEC, [&] { return launch_axpy<T>(S, av.data(), Pd, S, vseg(), st); });
+            run(KC_VEC, [&] { return launch_axpy<T>(Q, av.data(), HP, Q, vseg(), st); });
+            its = it;
+            if (std::sqrt(inner(Q, Q)) <= tol * gn) break;
+            precond_keep(Q, Z, false);
+            const double rz_new = -gs_s[0];
+            const std::vector<double> bv(1, rz_new / rz);
+            run(KC_VEC, [&] { return launch_axpy<T>(Z, bv.data(), Pd, Pd, vseg(), st); });
+            rz = rz_new;
+        }
+        // line search from rho = 1 along s (regulariser as a quadratic in rho)
+        if (vh_of != V) {
+            spectrum_of(V);
+            reg_s[0] = cell / double(Nt) * fetch(R_REG, 1)[0];
+            reg_from_device = false;
+        }
+        if (umax_of != V) set_bounds(V, velocity_max(V));
+        const double R0 = reg_s[0], um0 = umax;
+        const double gs = inner(G, S);
+        const T* sin_[3] = {comp(S, 0), comp(S, 1), d == 3 ? comp(S, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, sin_, sk, d, st); });
+        run(KC_REDUCE, [&] {
+            return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
+        });
+        const double smx = velocity_max(S);
+        const double* cr = fetch(R_CROSS, 2);
+        const double cA = cell / double(Nt) * cr[0], cB = cell / double(Nt) * cr[1];
+        T* q = static_cast<T*>(qb->p);
+        double rho = 1.0, Jq = 0.0, Rq = R0;
+        int trials = 0;
+        bool ok = false;
+        for (int t = 0; t <= p.max_backtracks; ++t) {
+            ++trials;
+            Rq = R0 + 2.0 * rho * cA + rho * rho * cB;
+            const double bound = Jcur[0] + p.c_armijo * rho * gs;
+            if (0.5 * alpha_s[0] * Rq >= bound) {
+                rho *= 0.5;
+                continue;
+            }
+            const std::vector<double> rv1(1, rho);
+            run(KC_VEC, [&] { return launch_axpy<T>(V, rv1.data(), S, q, vseg(), st); });
+            objective_trial(q, std::vector<double>(1, Rq), um0 + rho * smx);
+            Jq = J_s[0];
+            if (Jq < bound) {
+                ok = true;
+                break;
+            }
+            rho *= 0.5;
+        }
+        info[0].n_trials = trials;
+        if (!ok) throw Error(GANMRES_ELINESEARCH, "Armijo condition not met");
+        const std::vector<double> rv1(1, rho);
+        run(KC_SPEC, [&] { return launch_spec_axpy<T>(dm, d, vh, rv1.data(), sk, st); });
+        vh_of = q;
+        reg_s[0] = Rq;
+        reg_from_device = false;
+        std::swap(ring_v[0], qb);  // v^{k+1} = q, forward solve kept
+        gradient(rv(0), rg(0), true);
+        ++ngrad;
+        info[0].step_kind = GANMRES_STEP_NEWTON;
+        info[0].n_beta = its;
+        finish_step(p, v, rv(0), rg(0), J_s, std::vector<double>(1, Jq), std::vector<double>(1, rho),
+                    ngrad, info);
     }
 
     int count() const override { return nb; }
@@ -927,9 +1139,10 @@ class Problem : public ProblemBase {
         if (wcap == w && acc_cap == acc) return;
         if (started) throw Error(GANMRES_EINVAL, "window or accelerator changed during a solve; reset first");
         const bool aa = acc == GANMRES_ACCEL_AA;
+        const bool newton = acc == GANMRES_ACCEL_NK;
         ring_v.clear();
         ring_g.clear();
-        for (int i = 0; i < (aa ? 2 : w + 2); ++i) {
+        for (int i = 0; i < (aa || newton ? 2 : w + 2); ++i) {
             ring_v.emplace_back(new DevBuf);
             ring_v.back()->alloc(sizeof(T) * d * N);
             ring_g.emplace_back(new DevBuf);
@@ -937,7 +1150,7 @@ class Problem : public ProblemBase {
         }
         aa_r.clear();
         aa_q.clear();
-        for (int i = 0; i < (aa ? w + 1 : 0); ++i) {
+        for (int i = 0; i < (aa ? w + 1 : (newton ? 1 : 0)); ++i) {
             aa_r.emplace_back(new DevBuf);
             aa_r.back()->alloc(sizeof(T) * d * N);
             aa_q.emplace_back(new DevBuf);
@@ -1128,9 +1341,10 @@ class Problem : public ProblemBase {
     }
 
     void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) override {
-        ensure_solver(p.w, p.accel);
+        ensure_solver(p.accel == GANMRES_ACCEL_NK ? 0 : p.w, p.accel);
         for (int i = 0; i < nb; ++i) info[i] = ganmres_step_info{};
         if (p.accel == GANMRES_ACCEL_AA) step_aa(p, v, info);
+        else if (p.accel == GANMRES_ACCEL_NK) step_nk(p, v, info);
         else step_ngmres(p, v, info);
     }
 
@@ -1393,9 +1607,12 @@ int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs)
 int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info) {
     if (!h || !p || !v) return GANMRES_EINVAL;
-    if (p->w < 0 || p->w > GANMRES_MAX_WINDOW || p->sigma < 0 || p->tau < 0 ||
-        (p->sigma + p->tau) == 0 || p->n_iter < 1 || p->max_backtracks < 0 ||
-        (p->accel != GANMRES_ACCEL_NGMRES && p->accel != GANMRES_ACCEL_AA)) {
+    const bool mixing = p->accel != GANMRES_ACCEL_NK;  // w, sigma and tau are used
+    if ((mixing && (p->w < 0 || p->w > GANMRES_MAX_WINDOW || p->sigma < 0 || p->tau < 0 ||
+                    (p->sigma + p->tau) == 0)) ||
+        p->n_iter < 1 || p->max_backtracks < 0 ||
+        (p->accel != GANMRES_ACCEL_NGMRES && p->accel != GANMRES_ACCEL_AA &&
+         p->accel != GANMRES_ACCEL_NK)) {
         h->err = "invalid solver parameters";
         return GANMRES_EINVAL;
     }
@@ -1416,6 +1633,14 @@ int ganmres_deformation(ganmres_handle* h, const void* v, void* det, double* sta
         return GANMRES_EINVAL;
     }
     return guarded(h, [&] { h->impl->deformation(v, det, stats); });
+}
+
+int ganmres_hessian_matvec(ganmres_handle* h, const void* v, const void* vt, void* out) {
+    if (!h || !v || !vt || !out || vt == out || v == out) {
+        if (h) h->err = "invalid arguments";
+        return GANMRES_EINVAL;
+    }
+    return guarded(h, [&] { h->impl->hessian_matvec(v, vt, out); });
 }
 
 int ganmres_solver_reset(ganmres_handle* h) {

@@ -98,10 +98,14 @@ def time_to_solution(torch, P, params):
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
     last = infos[-1]
-    return dict(seconds=round(t, 4), iterations=last.k,
-                rel_grad=last.ginf / last.g0inf, reached=bool(last.ginf <= params.eps_rel * last.g0inf),
-                grad_evals=sum(i.n_grad for i in infos) + 1,
-                obj_evals=sum(i.n_trials for i in infos), J=last.J)
+    out = dict(seconds=round(t, 4), iterations=last.k,
+               rel_grad=last.ginf / last.g0inf, reached=bool(last.ginf <= params.eps_rel * last.g0inf),
+               grad_evals=sum(i.n_grad for i in infos),   # includes g(v^0)
+               obj_evals=sum(i.n_trials for i in infos), J=last.J)
+    import paper_2510_08782_amd as gan
+    if params.accel == gan.ACCEL_NK:   # one Hessian matvec per CG iteration
+        out["hessian_matvecs"] = sum(i.n_beta for i in infos)
+    return out
 
 
 def algorithmic_bytes(kernel, wl, N, s):
@@ -318,6 +322,9 @@ def main():
     if not args.no_tts:
         log("time-to-1e-2, FP32 GA-NGMRES")
         extra["tts_fp32_ga_ngmres"] = time_to_solution(torch, P32, params)
+        log("time-to-1e-2, FP32 Gauss-Newton-Krylov baseline")
+        nk = gan.SolveParams(eps_rel=sv["eps_rel"], n_iter=sv["n_iter"], accel=gan.ACCEL_NK)
+        extra["tts_fp32_nk"] = time_to_solution(torch, P32, nk)
     extra["peak_workspace_bytes_fp32"] = P32.workspace_bytes()
     P32.close()
 

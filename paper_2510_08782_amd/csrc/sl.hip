@@ -131,6 +131,7 @@ struct Tile<T_, 3, S_, TZ_> {
     // LDS row pitch: the two rows a wavefront reads (lanes 0-31 and 32-63)
     // start half the banks apart
     static constexpr int PX = 48;
+    static constexpr int PZ = PX * RY;  // plane pitch
     static_assert(RX <= PX, "window wider than the row pitch");
     static constexpr int PTS = TZ;  // points per thread
 };
@@ -142,12 +143,13 @@ struct Tile<T_, 2, S_, TZ_> {
     static constexpr int S = S_;
     static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = 1;
     static constexpr int PX = RX;  // a wavefront reads one row
+    static constexpr int PZ = PX * RY;
     static constexpr int PTS = 8;
 };
 
 template <class C>
 constexpr size_t tile_lds_bytes() {
-    return sizeof(typename C::T) * C::PX * C::RY * C::RZ;
+    return sizeof(typename C::T) * C::PZ * C::RZ;
 }
 
 // g mod n in [0, n): the common in-range case costs one compare.
@@ -221,9 +223,12 @@ __device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], i
 // Global-to-LDS loads (global_load_lds_dword): a wavefront walks the rows of
 // the region and moves each row with one instruction per 64 dwords, lane l
 // writing dword l of the row; the wrapped x index of every lane is computed
-// once.  All of a wave's row loads are in flight together and no VGPRs hold
-// the data.  FP64 rows move as pairs of dwords.  The LDS layout keeps the
-// variant's full row pitch PX and plane pitch RY.  Ends with a barrier.
+// once.  The wave's rows are described in parallel, one row per lane (its
+// wrapped global offset and its LDS offset), and the issue loop only reads
+// them back from the lanes, so that it carries no division, wrap or branch
+// per row.  All of a wave's row loads are in flight together and no VGPRs
+// hold the data.  FP64 rows move as pairs of dwords.  The LDS layout keeps
+// the variant's row pitch PX and plane pitch PZ.  Ends with a barrier.
 template <class C, bool WAIT = true>
 __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ src,
                              typename C::T* lds, int x0, int y0, int z0, const Window& w) {
@@ -244,17 +249,49 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
         xin[u] = d < W * ex;
         goff[u] = W * wrapn(ox + d / W, dm.n[2]) + d % W;
     }
-    for (int r = wave; r < rows; r += NW) {
+    // this wave's rows are r = wave + NW i, i < cnt
+    const int cnt = rows > wave ? (rows - wave + NW - 1) / NW : 0;
+    for (int i0 = 0; i0 < cnt; i0 += 64) {
+        const int r = wave + NW * (i0 + lane);
         const int ry = r % ey, rz = r / ey;
-        const int gy = wrapn(oy + ry, dm.n[1]);
+        const int gy = pmod(oy + ry, dm.n[1]);
         // 2-D: axis 0 indexes independent slices (no interpolation across it)
-        const int gz = C::DIM == 3 ? wrapn(oz + rz, dm.n[0]) : z0;
-        // N < 2^31 elements
-        const unsigned* row = reinterpret_cast<const unsigned*>(src + (gz * dm.n[1] + gy) * dm.n[2]);
-        unsigned* dst = reinterpret_cast<unsigned*>(lds + (rz * C::RY + ry) * C::PX);
+        const int gz = C::DIM == 3 ? pmod(oz + rz, dm.n[0]) : z0;
+        const int grow = (gz * dm.n[1] + gy) * dm.n[2];  // elements; N < 2^31
+        const int lrow = rz * C::PZ + ry * C::PX;
+        const int m = min(64, cnt - i0);
+        // The row descriptions are read back from the lanes (readlane, wave
+        // uniform) before the loads are masked to the lanes inside the row:
+        // reading a lane's value under a mask that excludes it would read a
+        // register that lane never wrote.
+        int j = 0;
+        for (; j + 4 <= m; j += 4) {
+            int go[4], lo[4];
 #pragma unroll
-        for (int u = 0; u < XP; ++u)
-            if (xin[u]) __builtin_amdgcn_global_load_lds(row + goff[u], dst + 64 * u, 4, 0, 0);
+            for (int q = 0; q < 4; ++q) {
+                go[q] = __builtin_amdgcn_readlane(grow, j + q);
+                lo[q] = __builtin_amdgcn_readlane(lrow, j + q);
+            }
+#pragma unroll
+            for (int u = 0; u < XP; ++u)
+                if (xin[u]) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        __builtin_amdgcn_global_load_lds(
+                            reinterpret_cast<const unsigned*>(src + go[q]) + goff[u],
+                            reinterpret_cast<unsigned*>(lds + lo[q]) + 64 * u, 4, 0, 0);
+                }
+        }
+        for (; j < m; ++j) {
+            const int go = __builtin_amdgcn_readlane(grow, j);
+            const int lo = __builtin_amdgcn_readlane(lrow, j);
+#pragma unroll
+            for (int u = 0; u < XP; ++u)
+                if (xin[u])
+                    __builtin_amdgcn_global_load_lds(reinterpret_cast<const unsigned*>(src + go) + goff[u],
+                                                     reinterpret_cast<unsigned*>(lds + lo) + 64 * u, 4, 0,
+                                                     0);
+        }
     }
     if constexpr (WAIT) {
         __builtin_amdgcn_s_waitcnt(0);
@@ -292,7 +329,7 @@ __device__ inline Stencil<typename C::T> lds_stencil(const Window& win, int lx, 
     const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], st.wy);
     if constexpr (C::DIM == 3) {
         const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], st.wz);
-        st.base = (bz * C::RY + by) * C::PX + bx;
+        st.base = bz * C::PZ + by * C::PX + bx;
     } else {
         st.base = by * C::PX + bx;
     }
@@ -312,7 +349,7 @@ __device__ inline typename C::T lds_interp(const typename C::T* lds,
             T sa = T(0);
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const T* row = base + (a * C::RY + b) * C::PX;
+                const T* row = base + a * C::PZ + b * C::PX;
                 sa += st.wy[b] *
                       (st.wx[0] * row[0] + st.wx[1] * row[1] + st.wx[2] * row[2] + st.wx[3] * row[3]);
             }
@@ -579,7 +616,7 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
     typename C::T s2, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
     using T = typename C::T;
     constexpr int DIM = C::DIM;
-    constexpr int PLANE = C::PX * C::RY * C::RZ;  // elements per staged component
+    constexpr int PLANE = C::PZ * C::RZ;  // elements per staged component
     extern __shared__ double2 sl_smem[];
     T* lds = reinterpret_cast<T*>(sl_smem);
     __shared__ int red[6 * (kThreads / 64)];

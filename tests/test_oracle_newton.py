@@ -104,3 +104,93 @@ def test_nk_reduces_the_gradient_in_few_iterations():
     assert [r.rho for r in res.records] == [1.0] * len(res.records)   # full Newton steps
     Js = [r.J for r in res.records]
     assert all(Js[i + 1] < Js[i] for i in range(len(Js) - 1))
+
+
+# ---- preconditioners of the Newton step (h0rpc, 2lrpcsym) ---------------------
+def test_gmres_solves_dense_nonsymmetric_systems():
+    rng = np.random.default_rng(5)
+    n = 30
+    A = 3.0 * np.eye(n) + rng.standard_normal((n, n))
+    b = rng.standard_normal(n)
+    inner = lambda a, c: float(a @ c)
+    x, its = nk.gmres(lambda p: A @ p, b, inner, 1e-13, 60)
+    np.testing.assert_allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-12)
+    x, its = nk.gmres(lambda p: A @ p, b, inner, 1e-2, 60)
+    assert np.linalg.norm(b - A @ x) <= 1e-2 * np.linalg.norm(b) and its < n
+
+
+def test_h0_matvec_is_the_gauss_newton_hessian_at_zero_velocity():
+    P, _, d, e = smooth_case(32, 4)
+    for x in (d, e):
+        H0 = nk.h0_matvec(P, x)
+        np.testing.assert_allclose(H0, nk.gn_matvec(P, np.zeros_like(x), x), rtol=0,
+                                   atol=1e-12 * np.abs(H0).max())
+
+
+def test_h0_preconditioner_inverts_h0():
+    P, _, d, _ = smooth_case(16, 2)
+    z = nk.h0_precond_apply(P, d, tol=1e-12, maxit=400)
+    np.testing.assert_allclose(nk.h0_matvec(P, z), d, rtol=0, atol=1e-9 * np.abs(d).max())
+
+
+def test_restriction_and_prolongation_are_spectral():
+    fine, coarse = (24, 32), (12, 16)
+    xf, xc = grid_x(fine), grid_x(coarse)
+    f = lambda x: np.cos(2 * x[0] - 3 * x[1]) + 0.5 * np.sin(5 * x[0]) + 0.2 * np.cos(7 * x[1] + 1)
+    np.testing.assert_allclose(nk.restrict(f(xf), coarse), f(xc), atol=1e-13)
+    np.testing.assert_allclose(nk.prolong(f(xc), fine), f(xf), atol=1e-13)
+    # modes the coarse grid drops (its Nyquist and beyond) are removed
+    g = lambda x: np.cos(6 * x[0]) + np.sin(11 * x[1])
+    np.testing.assert_allclose(nk.restrict(g(xf), coarse), 0.0, atol=1e-13)
+
+
+@pytest.mark.parametrize("incompressible", [False, True])
+def test_two_level_reduces_to_ireg_without_image_gradient(incompressible):
+    shape, nt = (16, 24), 2
+    P = TransportProblem(np.full(shape, 2.0), np.full(shape, 1.0), nt, 3e-2, 2,
+                         incompressible=incompressible)
+    x = grid_x(shape)
+    v = np.stack([0.3 * np.sin(x[1]), 0.2 * np.cos(x[0])])
+    r = np.stack([np.cos(2 * x[0] + x[1]) + 0.3 * np.sin(7 * x[1]), np.sin(x[0] - 3 * x[1]) + 1.0])
+    z = nk.TwoLevel(P, v).apply(r)
+    np.testing.assert_allclose(z, nk.precond_apply(P, r), rtol=0, atol=1e-12)
+    if incompressible:
+        assert np.abs(sp.divergence(P.grid, z)).max() < 1e-12
+
+
+@pytest.fixture(scope="module")
+def newton_system_64():
+    wl = synth.workload("c0", shape=(64, 64))
+    gen = TransportProblem(wl.m0, wl.m0, wl.nt, wl.alpha, wl.reg_order)
+    P = TransportProblem(wl.m0, gen.forward(wl.vstar)[-1], wl.nt, 1e-3, wl.reg_order)
+    v = 0.5 * wl.vstar
+    _, g, st = P.gradient(v, return_states=True)
+    return P, v, g, st
+
+
+def test_preconditioners_cut_the_cg_iterations(newton_system_64):
+    """A tight solve of one Newton system (64^2, alpha = 1e-3): the zero-velocity
+    Hessian and the two-level preconditioner need a fraction of the iterations
+    of the regulariser preconditioner (a wrong sign or a broken operator in
+    either makes it useless or divergent)."""
+    P, v, g, st = newton_system_64
+    H = lambda x: nk.gn_matvec(P, v, x, st)
+    its = {}
+    for name, Minv, flex in (("ireg", lambda r: nk.precond_apply(P, r), False),
+                             ("h0rpc", lambda r: nk.h0_precond_apply(P, r), True),
+                             ("2lrpcsym", nk.TwoLevel(P, v).apply, True)):
+        x, its[name] = nk.pcg(H, Minv, P.grid.inner, -g, 1e-6, 300, flexible=flex)
+        res = H(x) + g
+        assert np.sqrt(P.grid.inner(res, res) / P.grid.inner(g, g)) <= 1e-6
+    assert its["h0rpc"] <= its["ireg"] / 3 and its["2lrpcsym"] <= its["ireg"] / 2, its
+
+
+def test_nk_converges_with_every_preconditioner():
+    wl = synth.workload("c0", shape=(32, 32))
+    gen = TransportProblem(wl.m0, wl.m0, wl.nt, wl.alpha, wl.reg_order)
+    P = TransportProblem(wl.m0, gen.forward(wl.vstar)[-1], wl.nt, 1e-3, wl.reg_order)
+    for pc in nk.PRECONDITIONERS:
+        res = nk.nk_solve(P, eps_rel=1e-2, n_iter=20, precond=pc)
+        assert res.records[-1].ginf <= 1e-2 * res.g0inf, pc
+        Js = [r.J for r in res.records]
+        assert all(Js[i + 1] < Js[i] for i in range(len(Js) - 1)), pc

@@ -57,6 +57,7 @@ enum { GANMRES_F32 = 0, GANMRES_F64 = 1 };
 enum { GANMRES_VARIANT_GA = 0, GANMRES_VARIANT_ALT = 1 };
 enum { GANMRES_STEP_NGMRES = 0, GANMRES_STEP_FP = 1, GANMRES_STEP_AA = 2, GANMRES_STEP_NEWTON = 3 };
 enum { GANMRES_ACCEL_NGMRES = 0, GANMRES_ACCEL_AA = 1, GANMRES_ACCEL_NK = 2 };
+enum { GANMRES_PC_IREG = 0, GANMRES_PC_H0RPC = 1, GANMRES_PC_2LRPCSYM = 2 };
 
 typedef struct ganmres_handle ganmres_handle;
 
@@ -89,6 +90,10 @@ typedef struct {
                               alternation: GA-AA) or GANMRES_ACCEL_NK (the
                               Gauss-Newton-Krylov baseline, Appendix A; w,
                               sigma, tau, variant and rho_cap unused)           */
+    int nk_precond;        /* GANMRES_ACCEL_NK: preconditioner of the Newton
+                              step, GANMRES_PC_IREG ((alpha L)^-1),
+                              GANMRES_PC_H0RPC or GANMRES_PC_2LRPCSYM (see
+                              ganmres_newton_precond)                           */
 } ganmres_solver_params;
 
 #define GANMRES_MAX_WINDOW 64
@@ -188,7 +193,7 @@ int ganmres_apply_precond(ganmres_handle* h, const void* g, void* s, double* gs)
  * ganmres_hessian_matvec) with the preconditioner (alpha L_p)^-1, stopped when
  * ||r||_h <= min(1/2, sqrt(||g||_h / ||g(v^0)||_h)) ||g||_h or after 50
  * iterations, then Armijo backtracking from rho = 1 (advection model, full
- * history, single problem).
+ * history, single problem); p->nk_precond selects the preconditioner.
  * Errors: GANMRES_EINVAL (w < 0 or > GANMRES_MAX_WINDOW, sigma = tau = 0,
  * negative counts, unknown accel, accel or w changed without a reset,
  * GANMRES_ACCEL_NK outside its setting), GANMRES_ELINESEARCH, GANMRES_ELSQ,
@@ -223,6 +228,29 @@ int ganmres_deformation(ganmres_handle* h, const void* v, void* det, double* sta
  * problem only.  The call replaces the handle's adjoint fields.
  * Errors: GANMRES_EINVAL (continuity model, checkpoint_every > 1, a batch). */
 int ganmres_hessian_matvec(ganmres_handle* h, const void* v, const void* vt, void* out);
+
+/* Apply a preconditioner of the Newton step at velocity v (Appendix A,
+ * "Preconditioning"): z = M^-1 r.  which:
+ *   GANMRES_PC_IREG      M = alpha L_p ([P] when incompressible);
+ *   GANMRES_PC_H0RPC     M = H0, the Gauss-Newton Hessian at v = 0,
+ *                        H0 z = alpha L z + [P] grad m0 (grad m0 . z), inverted
+ *                        by GMRES on (alpha L)^-1 H0 z = (alpha L)^-1 r;
+ *   GANMRES_PC_2LRPCSYM  two-level: the low band of the symmetric
+ *                        regularisation-preconditioned Hessian
+ *                        I + Hreg^-1/2 H_data Hreg^-1/2 (Hreg = alpha L),
+ *                        discretised on the grid with half the cells per axis
+ *                        (images and v restricted spectrally, the coarse
+ *                        Nyquist modes dropped) and inverted by CG there; the
+ *                        high band takes Hreg^-1:
+ *                        z = prolong(Hreg^-1/2 y) + P_hf Hreg^-1 r.
+ * The inner solves stop at a relative residual of 1e-1 or after 10
+ * iterations (the Newton-Krylov iteration of ganmres_step uses the flexible
+ * CG update with the last two).  v, r, z: device velocities, z aliasing
+ * neither.  The advection model with the full state history on a single
+ * problem; 2LRPCSYM needs even sizes of at least 8.  The call replaces the
+ * handle's adjoint fields.
+ * Errors: GANMRES_EINVAL. */
+int ganmres_newton_precond(ganmres_handle* h, int which, const void* v, const void* r, void* z);
 
 /* Forget the solver state (k, rho, history); the next ganmres_step starts a
  * new solve from the v it is given. */

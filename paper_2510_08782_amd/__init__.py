@@ -25,6 +25,7 @@ F32, F64 = 0, 1
 VARIANT_GA, VARIANT_ALT = 0, 1
 STEP_NGMRES, STEP_FP, STEP_AA, STEP_NEWTON = 0, 1, 2, 3
 ACCEL_NGMRES, ACCEL_AA, ACCEL_NK = 0, 1, 2
+PC_IREG, PC_H0RPC, PC_2LRPCSYM = 0, 1, 2
 MAX_WINDOW = 64
 
 ERRORS = {
@@ -51,7 +52,8 @@ class SolverParams(ctypes.Structure):
     _fields_ = [("w", ctypes.c_int), ("sigma", ctypes.c_int), ("tau", ctypes.c_int),
                 ("eps_rel", ctypes.c_double), ("n_iter", ctypes.c_int),
                 ("c_armijo", ctypes.c_double), ("max_backtracks", ctypes.c_int),
-                ("rho_cap", ctypes.c_double), ("variant", ctypes.c_int), ("accel", ctypes.c_int)]
+                ("rho_cap", ctypes.c_double), ("variant", ctypes.c_int), ("accel", ctypes.c_int),
+                ("nk_precond", ctypes.c_int)]
 
 
 class StepInfo(ctypes.Structure):
@@ -81,6 +83,7 @@ def lib():
     L.ganmres_batch_values.argtypes = [vp, dp, dp]
     L.ganmres_deformation.argtypes = [vp, vp, vp, dp]
     L.ganmres_hessian_matvec.argtypes = [vp, vp, vp, vp]
+    L.ganmres_newton_precond.argtypes = [vp, ip, vp, vp, vp]
     L.ganmres_destroy.argtypes = [vp]
     L.ganmres_last_error.argtypes = [vp]
     L.ganmres_last_error.restype = ctypes.c_char_p
@@ -120,11 +123,12 @@ class SolveParams:
     rho_cap: float = 0.0
     variant: int = VARIANT_GA
     accel: int = ACCEL_NGMRES
+    nk_precond: int = PC_IREG
 
     def to_c(self):
         return SolverParams(self.w, self.sigma, self.tau, self.eps_rel, self.n_iter,
                             self.c_armijo, self.max_backtracks, self.rho_cap, self.variant,
-                            self.accel)
+                            self.accel, self.nk_precond)
 
 
 class Problem:
@@ -222,6 +226,13 @@ class Problem:
         self._check(lib().ganmres_hessian_matvec(self.h, self._vec(v).data_ptr(),
                                                  self._vec(vt).data_ptr(), out.data_ptr()))
         return out
+
+    def newton_precond(self, which, v, r, z=None):
+        """z = M^-1 r for the Newton-step preconditioner `which` (PC_*) at velocity v."""
+        z = self.new_velocity() if z is None else self._vec(z)
+        self._check(lib().ganmres_newton_precond(self.h, int(which), self._vec(v).data_ptr(),
+                                                 self._vec(r).data_ptr(), z.data_ptr()))
+        return z
 
     def reset(self):
         self._check(lib().ganmres_solver_reset(self.h))

@@ -76,6 +76,9 @@ hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partia
 template <typename T>
 hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Seg& g,
                        hipStream_t st);
+// out[c] = g[c] sum_j g[j] x[j] pointwise (d components of n points each)
+template <typename T>
+hipError_t launch_outer(const T* g, const T* x, T* out, int d, long long n, hipStream_t st);
 // out = q + sum_k coef[k nseg + s] (q - x[k]) on segment s   (K <= 65; the
 // NGMRES / AA update; coef: device table)
 template <typename T>
@@ -130,6 +133,21 @@ hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<doubl
 template <typename T>
 hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
                                C2<T>* const* sh, C2<T>* const* keep, hipStream_t st);
+// sh[c] = sign (alpha lbar_p)^expo P gh[c] (P only when sp.leray; lbar_p: l_p
+// with its zero entry set to one); band_cut: the modes outside |k_i| <= n_i/2 - 1
+// are set to zero.
+template <typename T>
+hipError_t launch_spec_pow(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
+                           C2<T>* const* sh, double expo, double sign, int band_cut,
+                           hipStream_t st);
+// Half spectra between the grid df and dc (half the cells on every
+// interpolated axis): to_coarse: dst (coarse) = scale src (fine) on the coarse
+// space |k_i| <= dc.n_i/2 - 1, else dst (fine) = scale src (coarse) there;
+// every other destination entry is zero.
+template <typename T>
+hipError_t launch_spec_resample(const Dims& df, const Dims& dc, C2<T>* const* src,
+                                C2<T>* const* dst, int count, int to_coarse, double scale,
+                                hipStream_t st);
 // Per stacked problem s (one for 3-D): res[s] = sum w l_p Re(vh conj sh),
 // res[nseg + s] = sum w l_p |sh|^2 (full-spectrum sums)
 template <typename T>

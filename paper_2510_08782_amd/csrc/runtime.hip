@@ -195,6 +195,7 @@ class ProblemBase {
     virtual int count() const = 0;
     virtual void deformation(const void* v, void* det, double* stats) = 0;
     virtual void hessian_matvec(const void* v, const void* vt, void* out) = 0;
+    virtual void newton_precond(int which, const void* v, const void* r, void* z) = 0;
     virtual void values(double* J, double* mismatch) const = 0;
     virtual void reset() = 0;
     virtual void get_field(int which, int j, void* out) = 0;
@@ -884,7 +885,7 @@ class Problem : public ProblemBase {
 
     // H_gn[v] vt with the state history, departure points and adjoint factors of
     // v current
-    void gn_matvec(const void* v, const void* vt, void* out) {
+    void gn_matvec(const void* v, const void* vt, void* out, bool data_only = false) {
         ensure_matvec_buffers();
         ensure_Y(v);
         adj_valid = false;  // lamh is about to hold the incremental adjoint
@@ -930,16 +931,295 @@ class Problem : public ProblemBase {
             w[t] = -trap_weight(t);
         }
         body_force(mp, lp, w, false);
-        // assembly: alpha L vt + [P] b (FP64 spectrum of vt, as for v)
-        const T* vin[3] = {comp(vt, 0), comp(vt, 1), d == 3 ? comp(vt, 2) : nullptr};
-        run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vth, d, st); });
+        // assembly: alpha L vt + [P] b (FP64 spectrum of vt, as for v); data_only:
+        // [P] b alone (the data term of the two-level preconditioner)
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
-        run(KC_SPEC, [&] {
-            return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vth, wh, wh, st);
-        });
+        if (data_only) {
+            run(KC_SPEC, [&] {
+                return launch_spec_pow<T>(dm, specop(cfg.incompressible != 0), wh, wh, 0.0, 1.0, 0, st);
+            });
+        } else {
+            const T* vin[3] = {comp(vt, 0), comp(vt, 1), d == 3 ? comp(vt, 2) : nullptr};
+            run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vth, d, st); });
+            run(KC_SPEC, [&] {
+                return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vth, wh, wh, st);
+            });
+        }
         T* hout[3] = {comp(out, 0), comp(out, 1), d == 3 ? comp(out, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, hout, nullptr, 1.0 / Nt, d, st); });
+    }
+
+    // ---- preconditioners of the Newton step (Appendix A) ---------------------
+    // M^-1 r for "h0rpc" (GMRES on the zero-velocity Hessian in its left
+    // regularisation-preconditioned form) and "2lrpcsym" (CG on the
+    // symmetric regularisation-preconditioned Hessian of the problem on the
+    // grid with half the cells, high frequencies by (alpha L)^-1).  Both inner
+    // solves stop at a relative residual of kPcTol or after kPcMaxit
+    // iterations.  The callers hold q = -r, the negated PCG residual.
+    static constexpr int kPcMaxit = 10;
+    static constexpr double kPcTol = 1e-1;
+    std::vector<std::unique_ptr<DevBuf>> pc_bufs;
+    T* pc_alloc(long long elems) {
+        pc_bufs.emplace_back(new DevBuf);
+        pc_bufs.back()->alloc(sizeof(T) * (size_t)elems);
+        ws_bytes += sizeof(T) * elems;
+        return static_cast<T*>(pc_bufs.back()->p);
+    }
+    T* gm0 = nullptr;                 // grad m0
+    T* pcv[kPcMaxit + 1] = {};        // Arnoldi basis
+    T* pcw = nullptr;                 // GMRES work vector
+    T* pcx = nullptr;                 // pointwise data term
+    T* qold = nullptr;                // previous -r of the flexible PCG
+
+    void ensure_h0() {
+        if (gm0) return;
+        ensure_matvec_buffers();
+        gm0 = pc_alloc(d * N);
+        const double one = 1.0;
+        for (int c = 0; c < d; ++c) {
+            const T* f = m0;
+            run(KC_DERIV, [&] {
+                return launch_deriv_axis<T>(dm, plans, comp_axis(d, c), &f, nullptr, &one, 1, 0,
+                                            gm0 + (long long)c * N, st);
+            });
+        }
+        for (int i = 0; i <= kPcMaxit; ++i) pcv[i] = pc_alloc(d * N);
+        pcw = pc_alloc(d * N);
+        pcx = pc_alloc(d * N);
+    }
+
+    // out = (alpha L)^-1 [P] H0 x, H0 x = alpha L x + [P] grad m0 (grad m0 . x)
+    void h0_left(const T* x, T* out) {
+        run(KC_VEC, [&] { return launch_outer<T>(gm0, x, pcx, d, N, st); });
+        const T* xin[3] = {comp(x, 0), comp(x, 1), d == 3 ? comp(x, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, xin, vth, d, st); });
+        const T* gin[3] = {comp(pcx, 0), comp(pcx, 1), d == 3 ? comp(pcx, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
+        const SpecOpParams sp = specop(cfg.incompressible != 0);
+        run(KC_SPEC, [&] { return launch_spec_gradient<T>(dm, sp, vth, wh, wh, st); });
+        // spec_precond gives -(alpha L)^-1 [P]: the inverse transform flips the sign
+        run(KC_SPEC, [&] { return launch_spec_precond<T>(dm, sp, wh, wh, nullptr, st); });
+        T* o[3] = {comp(out, 0), comp(out, 1), d == 3 ? comp(out, 2) : nullptr};
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, o, nullptr, -1.0 / Nt, d, st); });
+    }
+
+    // z = H0^-1 r approximately: GMRES from 0 on (alpha L)^-1 H0 z = (alpha L)^-1 r
+    // (Arnoldi with modified Gram-Schmidt, Givens rotations on the host)
+    void h0_precond(const T* q, T* z) {
+        ensure_h0();
+        const int m = kPcMaxit;
+        T* bvec = pcv[0];
+        precond_keep(q, bvec, false);  // (alpha L)^-1 [P] r, r = -q
+        HIPCHK(hipMemsetAsync(z, 0, sizeof(T) * d * N, st));
+        const double bn = std::sqrt(inner(bvec, bvec));
+        if (bn == 0.0) return;
+        std::vector<double> s1(1, 1.0 / bn - 1.0);
+        run(KC_VEC, [&] { return launch_axpy<T>(bvec, s1.data(), bvec, pcv[0], vseg(), st); });
+        std::vector<double> H((m + 1) * m, 0.0), cs(m, 0.0), sn(m, 0.0), e(m + 1, 0.0);
+        auto Hij = [&](int i, int j) -> double& { return H[i * m + j]; };
+        e[0] = bn;
+        int its = 0;
+        for (int j = 0; j < m; ++j) {
+            h0_left(pcv[j], pcw);
+            for (int i = 0; i <= j; ++i) {
+                const double hij = inner(pcw, pcv[i]);
+                Hij(i, j) = hij;
+                const std::vector<double> mh(1, -hij);
+                run(KC_VEC, [&] { return launch_axpy<T>(pcw, mh.data(), pcv[i], pcw, vseg(), st); });
+            }
+            const double hn = std::sqrt(inner(pcw, pcw));
+            Hij(j + 1, j) = hn;
+            for (int i = 0; i < j; ++i) {
+                const double t = cs[i] * Hij(i, j) + sn[i] * Hij(i + 1, j);
+                Hij(i + 1, j) = -sn[i] * Hij(i, j) + cs[i] * Hij(i + 1, j);
+                Hij(i, j) = t;
+            }
+            const double den = std::hypot(Hij(j, j), Hij(j + 1, j));
+            cs[j] = Hij(j, j) / den;
+            sn[j] = Hij(j + 1, j) / den;
+            Hij(j, j) = den;
+            Hij(j + 1, j) = 0.0;
+            e[j + 1] = -sn[j] * e[j];
+            e[j] = cs[j] * e[j];
+            its = j + 1;
+            if (std::fabs(e[j + 1]) <= kPcTol * bn || hn == 0.0) break;
+            const std::vector<double> sc(1, 1.0 / hn - 1.0);
+            run(KC_VEC, [&] { return launch_axpy<T>(pcw, sc.data(), pcw, pcv[j + 1], vseg(), st); });
+        }
+        std::vector<double> y(its, 0.0);
+        for (int i = its - 1; i >= 0; --i) {
+            double t = e[i];
+            for (int k2 = i + 1; k2 < its; ++k2) t -= Hij(i, k2) * y[k2];
+            y[i] = t / Hij(i, i);
+        }
+        for (int i = 0; i < its; ++i) {
+            const std::vector<double> yi(1, y[i]);
+            run(KC_VEC, [&] { return launch_axpy<T>(z, yi.data(), pcv[i], z, vseg(), st); });
+        }
+    }
+
+    // -- two-level -------------------------------------------------------------
+    std::unique_ptr<Problem<T>> coarse;
+    T *cv = nullptr, *cb = nullptr, *cy = nullptr, *cr = nullptr, *cp = nullptr, *cap = nullptr,
+      *ct = nullptr, *cd = nullptr;
+    const void* coarse_of = nullptr;  // fine velocity whose coarse state is current
+
+    // coarse (d_out components) = restriction of fine (count fields of N)
+    void restrict_to(const T* const* fine, T* const* out, int count, bool pow_half) {
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, fine, wh, count, st); });
+        Problem<T>& C = *coarse;
+        run(KC_SPEC, [&] {
+            return launch_spec_resample<T>(dm, C.dm, wh, C.wh, count, 1, double(C.N) / double(N), st);
+        });
+        if (pow_half)
+            run(KC_SPEC, [&] {
+                return launch_spec_pow<T>(C.dm, C.specop(cfg.incompressible != 0), C.wh, C.wh, -0.5,
+                                          1.0, 1, st);
+            });
+        run(KC_IRFFT, [&] { return launch_irfft<T>(C.dm, C.plans, C.wh, out, nullptr, 1.0 / C.N, count, st); });
+    }
+
+    void ensure_coarse() {
+        if (coarse) return;
+        for (int a = 0; a < d; ++a)
+            if (cfg.n[a] % 2 != 0 || cfg.n[a] < 8)
+                throw Error(GANMRES_EINVAL,
+                            "the two-level preconditioner halves every axis: sizes must be even "
+                            "and at least 8");
+        ganmres_config cc = cfg;
+        for (int a = 0; a < d; ++a) cc.n[a] = cfg.n[a] / 2;
+        cc.checkpoint_every = 1;
+        // the images passed here only fill the buffers; they are replaced below
+        coarse.reset(new Problem<T>(cc, m0, m1, st));
+        Problem<T>& C = *coarse;
+        T* o0[1] = {C.m0};
+        const T* i0[1] = {m0};
+        restrict_to(i0, o0, 1, false);
+        T* o1[1] = {C.m1};
+        const T* i1[1] = {m1};
+        restrict_to(i1, o1, 1, false);
+        HIPCHK(hipMemcpyAsync(C.mstate(0), C.m0, sizeof(T) * C.N, hipMemcpyDeviceToDevice, st));
+        cv = C.alloc_T(d * C.N);
+        cb = C.alloc_T(d * C.N);
+        cy = C.alloc_T(d * C.N);
+        cr = C.alloc_T(d * C.N);
+        cp = C.alloc_T(d * C.N);
+        cap = C.alloc_T(d * C.N);
+        ct = C.alloc_T(d * C.N);
+        cd = C.alloc_T(d * C.N);
+        coarse_of = nullptr;
+    }
+
+    // the coarse problem at the restriction of v (its state history)
+    void coarse_at(const void* v) {
+        ensure_coarse();
+        Problem<T>& C = *coarse;
+        const T* vin[3] = {comp(v, 0), comp(v, 1), d == 3 ? comp(v, 2) : nullptr};
+        T* vo[3] = {C.comp(cv, 0), C.comp(cv, 1), d == 3 ? C.comp(cv, 2) : nullptr};
+        restrict_to(vin, vo, d, false);
+        C.prepare(cv, true);
+        C.forward();
+        C.fwd_valid = true;
+        C.fwd_v = cv;
+        coarse_of = v;
+    }
+
+    // out = (alpha L)^-1/2 [P] x on the coarse space (the modes outside it removed)
+    static void reg_half(Problem<T>& C, const T* x, T* out) {
+        const T* xin[3] = {C.comp(x, 0), C.comp(x, 1), C.d == 3 ? C.comp(x, 2) : nullptr};
+        C.run(KC_RFFT, [&] { return launch_rfft<T, T>(C.dm, C.plans, xin, C.wh, C.d, C.st); });
+        C.run(KC_SPEC, [&] {
+            return launch_spec_pow<T>(C.dm, C.specop(C.cfg.incompressible != 0), C.wh, C.wh, -0.5,
+                                      1.0, 1, C.st);
+        });
+        T* o[3] = {C.comp(out, 0), C.comp(out, 1), C.d == 3 ? C.comp(out, 2) : nullptr};
+        C.run(KC_IRFFT, [&] { return launch_irfft<T>(C.dm, C.plans, C.wh, o, nullptr, 1.0 / C.N, C.d, C.st); });
+    }
+
+    // out = y + Hreg^-1/2 H_data,c Hreg^-1/2 y
+    void coarse_op(const T* y, T* out) {
+        Problem<T>& C = *coarse;
+        reg_half(C, y, ct);
+        C.gn_matvec(cv, ct, cd, true);
+        reg_half(C, cd, out);
+        const std::vector<double> one(1, 1.0);
+        C.run(KC_VEC, [&] { return launch_axpy<T>(out, one.data(), y, out, C.vseg(), C.st); });
+    }
+
+    // z = M^-1 r for the two-level preconditioner at the velocity of the last coarse_at
+    void twolevel_precond(const T* q, T* z) {
+        Problem<T>& C = *coarse;
+        precond_keep(q, z, false);  // (alpha L)^-1 [P] r
+        // coarse right-hand side from q: b_q = Hreg^-1/2 restrict(q)
+        const T* qin[3] = {comp(q, 0), comp(q, 1), d == 3 ? comp(q, 2) : nullptr};
+        T* bo[3] = {C.comp(cb, 0), C.comp(cb, 1), d == 3 ? C.comp(cb, 2) : nullptr};
+        restrict_to(qin, bo, d, true);
+        // CG (no preconditioner) on the coarse operator
+        HIPCHK(hipMemsetAsync(cy, 0, sizeof(T) * d * C.N, st));
+        const double bn = std::sqrt(C.inner(cb, cb));
+        if (bn > 0.0) {
+            HIPCHK(hipMemcpyAsync(cr, cb, sizeof(T) * d * C.N, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(cp, cb, sizeof(T) * d * C.N, hipMemcpyDeviceToDevice, st));
+            double rr = C.inner(cr, cr);
+            for (int it = 0; it < kPcMaxit; ++it) {
+                coarse_op(cp, cap);
+                const double pap = C.inner(cp, cap);
+                if (!(pap > 0.0)) break;
+                const std::vector<double> a(1, rr / pap), ma(1, -rr / pap);
+                C.run(KC_VEC, [&] { return launch_axpy<T>(cy, a.data(), cp, cy, C.vseg(), st); });
+                C.run(KC_VEC, [&] { return launch_axpy<T>(cr, ma.data(), cap, cr, C.vseg(), st); });
+                const double rr_new = C.inner(cr, cr);
+                if (std::sqrt(rr_new) <= kPcTol * bn) break;
+                const std::vector<double> be(1, rr_new / rr);
+                C.run(KC_VEC, [&] { return launch_axpy<T>(cr, be.data(), cp, cp, C.vseg(), st); });
+                rr = rr_new;
+            }
+        }
+        // z -= prolong(Hreg^-1/2 (y_q - b_q))  (the low band replaces that of (alpha L)^-1 r)
+        const std::vector<double> m1v(1, -1.0);
+        C.run(KC_VEC, [&] { return launch_axpy<T>(cy, m1v.data(), cb, ct, C.vseg(), st); });
+        const T* tin[3] = {C.comp(ct, 0), C.comp(ct, 1), d == 3 ? C.comp(ct, 2) : nullptr};
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(C.dm, C.plans, tin, C.wh, d, st); });
+        run(KC_SPEC, [&] {
+            return launch_spec_pow<T>(C.dm, C.specop(cfg.incompressible != 0), C.wh, C.wh, -0.5, 1.0,
+                                      1, st);
+        });
+        run(KC_SPEC, [&] {
+            return launch_spec_resample<T>(dm, C.dm, C.wh, wh, d, 0, double(N) / double(C.N), st);
+        });
+        T* zo[3] = {comp(z, 0), comp(z, 1), d == 3 ? comp(z, 2) : nullptr};
+        const T* za[3] = {comp(z, 0), comp(z, 1), d == 3 ? comp(z, 2) : nullptr};
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, zo, za, -1.0 / N, d, st); });
+    }
+
+    // z = M^-1 r (r = -q) for preconditioner `which`, with the state of v current
+    void apply_newton_pc(int which, const void* v, const T* q, T* z) {
+        if (which == GANMRES_PC_H0RPC) {
+            h0_precond(q, z);
+        } else if (which == GANMRES_PC_2LRPCSYM) {
+            if (coarse_of != v) coarse_at(v);
+            twolevel_precond(q, z);
+        } else {
+            precond_keep(q, z, false);
+        }
+    }
+
+    void newton_precond(int which, const void* v, const void* r, void* z) override {
+        check_newton_setup();
+        if (which != GANMRES_PC_IREG && which != GANMRES_PC_H0RPC && which != GANMRES_PC_2LRPCSYM)
+            throw Error(GANMRES_EINVAL, "unknown preconditioner");
+        ensure_matvec_buffers();
+        if (!qold) qold = pc_alloc(d * N);
+        // q = -r
+        const std::vector<double> m1v(1, -2.0);
+        run(KC_VEC, [&] {
+            return launch_axpy<T>(static_cast<const T*>(r), m1v.data(), static_cast<const T*>(r), qold,
+                                  vseg(), st);
+        });
+        coarse_of = nullptr;  // the caller's v may have changed
+        apply_newton_pc(which, v, qold, static_cast<T*>(z));
+        HIPCHK(hipStreamSynchronize(st));
     }
 
     // <a, b>_h (FP64; single problem)
@@ -970,14 +1250,20 @@ class Problem : public ProblemBase {
         T* HP = static_cast<T*>(aa_q[0]->p);
         const double gn = std::sqrt(inner(G, G));
         const double tol = std::min(0.5, std::sqrt(gn / nk_g0norm));
-        // CG from x = 0 on H x = b = -g.  Q holds -r (Q = g at the start), the
-        // preconditioner gives Z = -(alpha L)^-1 Q = M^-1 r and <r, z> = -<Q, Z>;
-        // the state history of V stays current through the iteration
+        // CG from x = 0 on H x = b = -g.  Q holds -r (Q = g at the start) and
+        // Z = M^-1 r, so <r, z> = -<Q, Z>.  With "ireg" (Z = -(alpha L)^-1 Q) the
+        // usual update; with the inner-solve preconditioners the flexible one,
+        // beta = <r_new - r_old, z_new> / <r_old, z_old>.  The state history of
+        // V stays current through the iteration.
+        const int pc = p.nk_precond;
+        const bool flexible = pc != GANMRES_PC_IREG;
+        if (flexible && !qold) qold = pc_alloc(d * N);
+        if (pc == GANMRES_PC_2LRPCSYM) coarse_at(V);
         HIPCHK(hipMemsetAsync(S, 0, sizeof(T) * d * N, st));
         HIPCHK(hipMemcpyAsync(Q, G, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
-        precond_keep(Q, Z, false);
+        apply_newton_pc(pc, V, Q, Z);
         HIPCHK(hipMemcpyAsync(Pd, Z, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
-        double rz = -gs_s[0];
+        double rz = flexible ? -inner(Q, Z) : -gs_s[0];
         int its = 0;
         for (int it = 1; it <= kCgMaxit; ++it) {
             gn_matvec(V, Pd, HP);
@@ -986,12 +1272,15 @@ class Problem : public ProblemBase {
             const double a = rz / pHp;
             const std::vector<double> av(1, a);
             run(KC_VEC, [&] { return launch_axpy<T>(S, av.data(), Pd, S, vseg(), st); });
+            if (flexible)
+                HIPCHK(hipMemcpyAsync(qold, Q, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
             run(KC_VEC, [&] { return launch_axpy<T>(Q, av.data(), HP, Q, vseg(), st); });
             its = it;
             if (std::sqrt(inner(Q, Q)) <= tol * gn) break;
-            precond_keep(Q, Z, false);
-            const double rz_new = -gs_s[0];
-            const std::vector<double> bv(1, rz_new / rz);
+            apply_newton_pc(pc, V, Q, Z);
+            const double rz_new = flexible ? -inner(Q, Z) : -gs_s[0];
+            const double beta = flexible ? (rz_new + inner(qold, Z)) / rz : rz_new / rz;
+            const std::vector<double> bv(1, beta);
             run(KC_VEC, [&] { return launch_axpy<T>(Z, bv.data(), Pd, Pd, vseg(), st); });
             rz = rz_new;
         }
@@ -1496,6 +1785,10 @@ static int guarded(ganmres_handle* h, F&& f) {
     }
 }
 
+// the Python binding mirrors these layouts
+static_assert(sizeof(ganmres_config) == 48, "ganmres_config layout");
+static_assert(sizeof(ganmres_solver_params) == 72, "ganmres_solver_params layout");
+
 static int create_impl(const ganmres_config* cfg, int count, const double* alpha, const void* m0,
                        const void* m1, void* stream, ganmres_handle** out) {
     if (!cfg || !m0 || !m1 || !out) {
@@ -1608,6 +1901,11 @@ int ganmres_step(ganmres_handle* h, const ganmres_solver_params* p, void* v,
                  ganmres_step_info* info) {
     if (!h || !p || !v) return GANMRES_EINVAL;
     const bool mixing = p->accel != GANMRES_ACCEL_NK;  // w, sigma and tau are used
+    if (!mixing && p->nk_precond != GANMRES_PC_IREG && p->nk_precond != GANMRES_PC_H0RPC &&
+        p->nk_precond != GANMRES_PC_2LRPCSYM) {
+        h->err = "unknown Newton-Krylov preconditioner";
+        return GANMRES_EINVAL;
+    }
     if ((mixing && (p->w < 0 || p->w > GANMRES_MAX_WINDOW || p->sigma < 0 || p->tau < 0 ||
                     (p->sigma + p->tau) == 0)) ||
         p->n_iter < 1 || p->max_backtracks < 0 ||
@@ -1641,6 +1939,14 @@ int ganmres_hessian_matvec(ganmres_handle* h, const void* v, const void* vt, voi
         return GANMRES_EINVAL;
     }
     return guarded(h, [&] { h->impl->hessian_matvec(v, vt, out); });
+}
+
+int ganmres_newton_precond(ganmres_handle* h, int which, const void* v, const void* r, void* z) {
+    if (!h || !v || !r || !z || r == z || v == z) {
+        if (h) h->err = "invalid arguments";
+        return GANMRES_EINVAL;
+    }
+    return guarded(h, [&] { h->impl->newton_precond(which, v, r, z); });
 }
 
 int ganmres_solver_reset(ganmres_handle* h) {

@@ -508,6 +508,89 @@ __global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, Sp
     }
 }
 
+// The coarse space of the two-level preconditioner on a grid of c_i cells per
+// axis: the wavenumbers |k_i| <= c_i/2 - 1 (the Nyquist modes, and for an odd
+// c_i the top pair, dropped, so that restriction and prolongation are exact
+// inverses on it).
+__device__ inline bool coarse_kept(int k, int c) { return 2 * (k < 0 ? -k : k) <= c - 2; }
+
+// sh[c] = sign (alpha lbar_p)^expo P gh[c]; with band_cut the modes outside
+// the coarse space of this grid are set to zero.
+template <typename T>
+__global__ void spec_pow_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, SpecPtrs<T> sh,
+                                double expo, double sign, int band_cut) {
+    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+         lin += (long long)gridDim.x * blockDim.x) {
+        const int i2 = (int)(lin % dm.n2h);
+        const long long rest = lin / dm.n2h;
+        const int i1 = (int)(rest % dm.n[1]), i0 = (int)(rest / dm.n[1]);
+        const int k0 = dm.dim == 3 ? wavenumber(i0, dm.n[0]) : 0;
+        const bool kept = (dm.dim == 2 || coarse_kept(k0, dm.n[0])) &&
+                          coarse_kept(wavenumber(i1, dm.n[1]), dm.n[1]) && coarse_kept(i2, dm.n[2]);
+        const KVec kv = kvec(dm, lin);
+        double l = ipow(kv.k2, sp.p);
+        if (l == 0.0) l = 1.0;
+        const T f = (band_cut && !kept) ? T(0) : T(sign * pow(seg_alpha(sp, dm, lin) * l, expo));
+        C2<T> g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
+        if (sp.leray) leray_point(kv, sp.dim, g);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            if (c < sp.dim) sh.spec[c][lin] = cscale(g[c], f);
+    }
+}
+
+// Half spectra between a grid and the grid with half the cells per axis,
+// on the coarse space; every other entry of the destination is zero.
+// restrict: coarse(k) = scale fine(k);  prolong: fine(k) = scale coarse(k).
+
+template <typename T>
+__global__ void spec_restrict_kernel(Dims df, Dims dc, SpecPtrs<T> fine, SpecPtrs<T> coarse,
+                                     int count, T scale) {
+    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dc.NH;
+         lin += (long long)gridDim.x * blockDim.x) {
+        const int i2 = (int)(lin % dc.n2h);
+        const long long rest = lin / dc.n2h;
+        const int i1 = (int)(rest % dc.n[1]), i0 = (int)(rest / dc.n[1]);
+        const int k0 = dc.dim == 3 ? wavenumber(i0, dc.n[0]) : 0;
+        const int k1 = wavenumber(i1, dc.n[1]);
+        const bool keep = (dc.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
+                          coarse_kept(i2, dc.n[2]);
+        long long src = 0;
+        if (keep) {
+            const int f0 = dc.dim == 3 ? (k0 < 0 ? k0 + df.n[0] : k0) : i0;
+            const int f1 = k1 < 0 ? k1 + df.n[1] : k1;
+            src = ((long long)f0 * df.n[1] + f1) * df.n2h + i2;
+        }
+        for (int c = 0; c < count; ++c)
+            coarse.spec[c][lin] = keep ? cscale(fine.spec[c][src], scale) : cmk(T(0), T(0));
+    }
+}
+
+template <typename T>
+__global__ void spec_prolong_kernel(Dims df, Dims dc, SpecPtrs<T> coarse, SpecPtrs<T> fine,
+                                    int count, T scale) {
+    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < df.NH;
+         lin += (long long)gridDim.x * blockDim.x) {
+        const int i2 = (int)(lin % df.n2h);
+        const long long rest = lin / df.n2h;
+        const int i1 = (int)(rest % df.n[1]), i0 = (int)(rest / df.n[1]);
+        const int k0 = df.dim == 3 ? wavenumber(i0, df.n[0]) : 0;
+        const int k1 = wavenumber(i1, df.n[1]);
+        const bool keep = (df.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
+                          coarse_kept(i2, dc.n[2]);
+        long long src = 0;
+        if (keep) {
+            const int c0 = df.dim == 3 ? (k0 < 0 ? k0 + dc.n[0] : k0) : i0;
+            const int c1 = k1 < 0 ? k1 + dc.n[1] : k1;
+            src = ((long long)c0 * dc.n[1] + c1) * dc.n2h + i2;
+        }
+        for (int c = 0; c < count; ++c)
+            fine.spec[c][lin] = keep ? cscale(coarse.spec[c][src], scale) : cmk(T(0), T(0));
+    }
+}
+
 // Cross terms of the regulariser along a line: with the half-spectrum
 // weights (1 at k2 = 0 and at the Nyquist index, else 2),
 //   res[0] = sum w l_p Re(vh conj(sh)),  res[1] = sum w l_p |sh|^2.
@@ -730,6 +813,39 @@ hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* co
 }
 
 template <typename T>
+hipError_t launch_spec_pow(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
+                           C2<T>* const* sh, double expo, double sign, int band_cut,
+                           hipStream_t st) {
+    SpecPtrs<T> a{}, b{};
+    for (int c = 0; c < sp.dim; ++c) {
+        a.spec[c] = gh[c];
+        b.spec[c] = sh[c];
+    }
+    spec_pow_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, expo, sign, band_cut);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spec_resample(const Dims& df, const Dims& dc, C2<T>* const* src,
+                                C2<T>* const* dst, int count, int to_coarse, double scale,
+                                hipStream_t st) {
+    if (count < 1 || count > 3 || df.dim != dc.dim) return hipErrorInvalidValue;
+    for (int a = 3 - df.dim; a < 3; ++a)
+        if (df.n[a] != 2 * dc.n[a]) return hipErrorInvalidValue;
+    if (df.dim == 2 && df.n[0] != dc.n[0]) return hipErrorInvalidValue;
+    SpecPtrs<T> s{}, d{};
+    for (int c = 0; c < count; ++c) {
+        s.spec[c] = src[c];
+        d.spec[c] = dst[c];
+    }
+    if (to_coarse)
+        spec_restrict_kernel<T><<<pointwise_blocks(dc.NH), 256, 0, st>>>(df, dc, s, d, count, T(scale));
+    else
+        spec_prolong_kernel<T><<<pointwise_blocks(df.NH), 256, 0, st>>>(df, dc, s, d, count, T(scale));
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>* const* vh,
                              C2<T>* const* sh, double* partial, double* res, hipStream_t st) {
     SpecPtrs<double> a{};
@@ -790,7 +906,11 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
     template hipError_t launch_spec_axpy<T>(const Dims&, int, C2<double>* const*, const double*,  \
                                             C2<T>* const*, hipStream_t);                          \
     template hipError_t launch_spec_regvalue<T>(const Dims&, const SpecOpParams&, C2<T>* const*,  \
-                                                double*, double*, hipStream_t);
+                                                double*, double*, hipStream_t);                   \
+    template hipError_t launch_spec_pow<T>(const Dims&, const SpecOpParams&, C2<T>* const*,       \
+                                           C2<T>* const*, double, double, int, hipStream_t);      \
+    template hipError_t launch_spec_resample<T>(const Dims&, const Dims&, C2<T>* const*,          \
+                                                C2<T>* const*, int, int, double, hipStream_t);
 GAN_INST(float)
 GAN_INST(double)
 #undef GAN_INST

@@ -132,6 +132,17 @@ __global__ void axpy_kernel(const T* __restrict__ a, SegCoef sc, const T* __rest
         out[base + i] = a[base + i] + k * b[base + i];
 }
 
+template <typename T>
+__global__ void outer_kernel(const T* __restrict__ g, const T* __restrict__ x, T* __restrict__ out,
+                             int d, long long n) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        T dot = T(0);
+        for (int j = 0; j < d; ++j) dot += g[j * n + i] * x[j * n + i];
+        for (int c = 0; c < d; ++c) out[c * n + i] = g[c * n + i] * dot;
+    }
+}
+
 constexpr int kMaxCombine = 65;
 template <typename T>
 struct CombineArgs {
@@ -330,6 +341,14 @@ hipError_t launch_axpy(const T* a, const double* s, const T* b, T* out, const Se
 }
 
 template <typename T>
+hipError_t launch_outer(const T* g, const T* x, T* out, int d, long long n, hipStream_t st) {
+    if (d < 1 || d > 3 || n < 1) return hipErrorInvalidValue;
+    const long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    outer_kernel<T><<<(unsigned)blocks, 256, 0, st>>>(g, x, out, d, n);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int K, T* out,
                           const Seg& g, hipStream_t st) {
     if (K < 0 || K > kMaxCombine || !seg_valid(g)) return hipErrorInvalidValue;
@@ -352,6 +371,7 @@ hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int
                                        hipStream_t);                                              \
     template hipError_t launch_combine<T>(const T*, const T* const*, const double*, int, T*,      \
                                           const Seg&, hipStream_t);                               \
+    template hipError_t launch_outer<T>(const T*, const T*, T*, int, long long, hipStream_t);     \
     template hipError_t launch_det_stats<T>(const T* const*, const double*, int, const Seg&, T*,  \
                                             double*, double*, hipStream_t);
 GAN_INST(float)

@@ -10,7 +10,7 @@ import paper_2510_08782_amd as gan
 def test_library_exports_every_header_symbol():
     lib = gan.lib()
     syms = gan.header_symbols()
-    assert len(syms) == 20
+    assert len(syms) == 21
     for name in syms:
         assert hasattr(lib, name), name
     for name in ["ganmres_eval_objective", "ganmres_eval_gradient", "ganmres_apply_precond",
@@ -26,7 +26,7 @@ def test_kernel_names_and_struct_layout():
     assert lib.ganmres_kernel_name(n) == b""
     # ctypes mirrors of the C structs: sizes as gcc lays them out on x86-64
     assert ctypes.sizeof(gan.Config) == 48
-    assert ctypes.sizeof(gan.SolverParams) == 64
+    assert ctypes.sizeof(gan.SolverParams) == 72
     assert ctypes.sizeof(gan.StepInfo) == 584
 
 

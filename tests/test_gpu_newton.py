@@ -174,3 +174,139 @@ def test_c2_full_size_hessian_properties_and_nk_step():
     assert info.J < J0 and info.ginf < info.g0inf
     assert info.n_beta >= 1 and info.step_kind == gan.STEP_NEWTON
     G.close()
+
+
+# ---- preconditioners of the Newton step ----------------------------------------
+PCS = {"ireg": 0, "h0rpc": 1, "2lrpcsym": 2}
+
+
+def data_term_lambda_max(P, iters=60):
+    """Largest eigenvalue of Hreg^-1/2 [P] grad m0 (grad m0 . ) Hreg^-1/2 (power iteration)."""
+    g = P.grid
+    gm = onk.sp.gradient(g, P.m0)
+    R = lambda x: onk.reg_inverse_sqrt(g, x, P.p, P.alpha, P.incompressible)
+
+    def op(x):
+        y = R(x)
+        dt = np.sum(gm * y, axis=0) * gm
+        return R(onk.sp.leray(g, dt) if P.incompressible else dt)
+
+    x = np.random.default_rng(0).standard_normal((g.d,) + g.shape)
+    lam = 0.0
+    for _ in range(iters):
+        y = op(x)
+        lam = np.sqrt(g.inner(y, y) / g.inner(x, x))
+        x = y / np.sqrt(g.inner(y, y))
+    return lam
+
+
+def oracle_pc(name, P, v, r):
+    if name == "ireg":
+        return onk.precond_apply(P, r)
+    if name == "h0rpc":
+        return onk.h0_precond_apply(P, r)
+    return onk.TwoLevel(P, v).apply(r)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("pc", list(PCS))
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_newton_preconditioner_parity(case, pc, prec):
+    """z = M^-1 r element by element against the oracle (the inner GMRES / coarse
+    CG with the same stopping rule)."""
+    name, shape, nt = case
+    say(f"case {name} shape {shape} nt {nt} {pc} {prec}")
+    wl = synth.workload(name, shape=shape)
+    P = as_precision(oracle_problem(wl, nt=nt), prec)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    G = make_gpu(P, dtype)
+    v = round_to(0.5 * wl.vstar, prec)
+    tol = TOL[prec]
+    if pc != "ireg":
+        # The inner solves work on I + Hreg^-1/2 H_data Hreg^-1/2 (or the
+        # left form, same spectrum): the relative error of their solution is up
+        # to kappa times that of the operator, one unit of rounding of the
+        # path's precision.  kappa = 1 + lambda_max, estimated by power
+        # iteration on the zero-velocity data term.
+        kappa = 1.0 + data_term_lambda_max(P)
+        eps = np.finfo(np.float64 if prec == "f64" else np.float32).eps
+        tol = max(tol, eps * kappa)
+        say(f"  kappa {kappa:.4g}, tolerance {tol:.2e}")
+    for seed in (31, 32):
+        r = round_to(smooth_direction(wl.shape, seed, wl.incompressible), prec)
+        zo = oracle_pc(pc, P, v, r)
+        zg = host(G.newton_precond(PCS[pc], dev(v, dtype), dev(r, dtype)))
+        err = rel(zg, zo)
+        say(f"  seed {seed}: rel err {err:.2e}")
+        assert err <= tol, (seed, err)
+    G.close()
+
+
+@pytest.mark.parametrize("pc", ["h0rpc", "2lrpcsym"])
+def test_nk_trajectory_parity_with_preconditioner_f64(pc):
+    """NK with the zero-velocity or the two-level preconditioner on the c0
+    recipe (64^2, FP64) against the oracle's loop, to ||g||_inf <= 1e-4 ||g_0||_inf."""
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c0")
+    P = oracle_problem(wl)
+    res = onk.nk_solve(P, eps_rel=1e-4, n_iter=8, keep_iterates=True, precond=pc)
+    G = make_gpu(P, torch.float64)
+    params = gan.SolveParams(eps_rel=1e-4, n_iter=8, accel=gan.ACCEL_NK, nk_precond=PCS[pc])
+    v = G.new_velocity()
+    for k in range(1, 9):
+        info = G.step(params, v)
+        rec = res.records[k - 1]
+        err = rel(host(v), res.iterates[k])
+        say(f"  k {k} J {info.J:.12e} / {rec.J:.12e} cg {info.n_beta}/{rec.cg_iters} "
+            f"rho {info.rho}/{rec.rho} iterate err {err:.2e}")
+        assert info.n_beta == rec.cg_iters
+        assert info.rho == rec.rho and info.n_trials == rec.trials
+        assert err <= 1e-8
+        assert abs(info.J - rec.J) <= 1e-10 * abs(rec.J)
+        if info.stop:
+            break
+    assert info.k == len(res.records)
+    G.close()
+
+
+def test_newton_preconditioner_errors():
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c0", shape=(27, 36))
+    P = oracle_problem(wl, nt=2)
+    G = make_gpu(P, torch.float64)
+    v = G.new_velocity()
+    r = dev(smooth_direction(wl.shape, 3), torch.float64)
+    with pytest.raises(gan.GanmresError) as ei:   # odd size: no half grid
+        G.newton_precond(gan.PC_2LRPCSYM, v, r)
+    assert ei.value.code == -1
+    with pytest.raises(gan.GanmresError):
+        G.newton_precond(7, v, r)
+    with pytest.raises(gan.GanmresError):
+        G.step(gan.SolveParams(n_iter=2, accel=gan.ACCEL_NK, nk_precond=9), v)
+    # the zero-velocity preconditioner has no size restriction
+    z = host(G.newton_precond(gan.PC_H0RPC, v, r))
+    assert rel(z, onk.h0_precond_apply(P, host(r))) <= 1e-10
+    G.close()
+
+
+@pytest.mark.parametrize("pc", ["h0rpc", "2lrpcsym"])
+def test_c2_full_size_nk_step_with_preconditioner(pc):
+    """128^3 incompressible FP32: one NK step from v = 0 with each inner-solve
+    preconditioner lowers J and the gradient, with no more CG iterations than
+    the regulariser preconditioner needs."""
+    import paper_2510_08782_amd as gan
+    wl = synth.workload("c2")
+    P = oracle_problem(wl)
+    its = {}
+    for name in ("ireg", pc):
+        G = make_gpu(P, torch.float32)
+        v0 = G.new_velocity()
+        info = G.step(gan.SolveParams(eps_rel=1e-3, n_iter=5, accel=gan.ACCEL_NK,
+                                      nk_precond=PCS[name]), v0)
+        say(f"  {name}: J {info.J:.6e} ginf {info.ginf:.3e} / {info.g0inf:.3e} cg {info.n_beta} "
+            f"rho {info.rho}")
+        its[name] = info.n_beta
+        J0 = G.eval_objective(G.new_velocity())
+        assert info.J < J0 and info.ginf < info.g0inf
+        G.close()
+    assert its[pc] <= its["ireg"]

@@ -322,9 +322,13 @@ def main():
     if not args.no_tts:
         log("time-to-1e-2, FP32 GA-NGMRES")
         extra["tts_fp32_ga_ngmres"] = time_to_solution(torch, P32, params)
-        log("time-to-1e-2, FP32 Gauss-Newton-Krylov baseline")
-        nk = gan.SolveParams(eps_rel=sv["eps_rel"], n_iter=sv["n_iter"], accel=gan.ACCEL_NK)
-        extra["tts_fp32_nk"] = time_to_solution(torch, P32, nk)
+        for pname, pc in (("ireg", gan.PC_IREG), ("h0rpc", gan.PC_H0RPC),
+                          ("2lrpcsym", gan.PC_2LRPCSYM)):
+            log(f"time-to-1e-2, FP32 Gauss-Newton-Krylov baseline, {pname}")
+            nk = gan.SolveParams(eps_rel=sv["eps_rel"], n_iter=sv["n_iter"], accel=gan.ACCEL_NK,
+                                 nk_precond=pc)
+            key = "tts_fp32_nk" if pc == gan.PC_IREG else f"tts_fp32_nk_{pname}"
+            extra[key] = time_to_solution(torch, P32, nk)
     extra["peak_workspace_bytes_fp32"] = P32.workspace_bytes()
     P32.close()
 

@@ -60,12 +60,14 @@ def run_steps(torch, P, params, v, nsteps):
     return ngrad, nobj
 
 
-def time_steps(torch, P, params, steps, warmup, timing=False):
+def time_steps(torch, P, params, steps, warmup, timing=False, classes=None):
+    """steps solver iterations after warmup; timing: bracket the launches of
+    `classes` (all when None) with HIP events and return the per-class report."""
     v = P.new_velocity()
     P.reset()
     run_steps(torch, P, params, v, warmup)
     if timing:
-        P.timing(True)
+        P.timing(True, classes)
         P.timing_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -290,14 +292,22 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
-    log(f"timing {args.steps} FP32 steps after {args.warmup} warmup")
-    dt, ngrad, nobj, rep = time_steps(torch, P32, params, args.steps, args.warmup, timing=True)
+    # Per-class breakdown from a pass with every launch bracketed by events;
+    # the timed region then brackets only the dominant class (each event pair
+    # costs the stream a few microseconds, so bracketing everything would slow
+    # the measured step by about 13%).
+    nb = min(args.steps, 10)
+    log(f"kernel breakdown: {nb} FP32 steps with every launch timed")
+    _, _, _, rep = time_steps(torch, P32, params, nb, args.warmup, timing=True)
+    dname = max(rep.items(), key=lambda kv: kv[1][0])[0]
+    log(f"timing {args.steps} FP32 steps after {args.warmup} warmup ({dname} launches timed)")
+    dt, ngrad, nobj, drep = time_steps(torch, P32, params, args.steps, args.warmup, timing=True,
+                                       classes=[dname])
     value = ngrad / dt
-    log(f"FP32: {ngrad} grads in {dt:.3f}s -> {value:.1f} grad/s ; kernels {rep}")
+    log(f"FP32: {ngrad} grads in {dt:.3f}s -> {value:.1f} grad/s")
 
     # dominant kernel of the timed region and its roofline
-    dom = max(rep.items(), key=lambda kv: kv[1][0])
-    dname, (dms, dcount) = dom
+    dms, dcount = drep[dname]
     bpl = algorithmic_bytes(dname, wl, N, 4)
     roofline = None
     if bpl is not None and dcount > 0:
@@ -311,6 +321,7 @@ def main():
                    "avg_us": round(1e3 * ms / c, 2) if c else None,
                    "share": round(ms / max(sum(x[0] for x in rep.values()), 1e-12), 4)}
                for k, (ms, c) in rep.items()}
+    kernels["_note"] = f"separate pass of {nb} steps with every launch timed"
     for kname in ("sl_step", "deriv_axis"):
         b = algorithmic_bytes(kname, wl, N, 4)
         if kname in rep and rep[kname][1]:

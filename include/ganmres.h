@@ -262,12 +262,16 @@ int ganmres_solver_reset(ganmres_handle* h);
  * gradient evaluation.  Errors: GANMRES_EINVAL, GANMRES_ESTATE. */
 int ganmres_get_field(ganmres_handle* h, int which, int j, void* out);
 
-/* Kernel timing.  With on = 1 the library brackets every launch with HIP
- * events on its stream and accumulates per-kernel-class device time.
+/* Kernel timing.  With on = 1 the library brackets every launch of the
+ * selected kernel classes (all by default) with HIP events on its stream and
+ * accumulates per-class device time.  ganmres_timing_select sets the classes
+ * (bit k of mask: class k); an event pair costs the stream a few microseconds,
+ * so a measurement that times one class should select only that one.
  * ganmres_timing_get returns the accumulated milliseconds and launch count of
  * class `kernel` (see ganmres_kernel_name) and the number of classes;
  * ganmres_timing_reset clears the accumulators. */
 int ganmres_timing_enable(ganmres_handle* h, int on);
+int ganmres_timing_select(ganmres_handle* h, unsigned mask);
 int ganmres_timing_reset(ganmres_handle* h);
 int ganmres_timing_get(ganmres_handle* h, int kernel, double* ms, long long* launches);
 int ganmres_kernel_count(void);

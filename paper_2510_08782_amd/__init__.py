@@ -95,6 +95,7 @@ def lib():
     L.ganmres_get_field.argtypes = [vp, ip, ip, vp]
     L.ganmres_timing_enable.argtypes = [vp, ip]
     L.ganmres_timing_reset.argtypes = [vp]
+    L.ganmres_timing_select.argtypes = [vp, ctypes.c_uint]
     L.ganmres_timing_get.argtypes = [vp, ip, dp, ctypes.POINTER(ctypes.c_longlong)]
     L.ganmres_kernel_count.argtypes = []
     L.ganmres_kernel_name.argtypes = [ip]
@@ -247,7 +248,16 @@ class Problem:
         return int(lib().ganmres_workspace_bytes(self.h))
 
     # -- timing ---------------------------------------------------------------
-    def timing(self, on=True):
+    def timing(self, on=True, classes=None):
+        """Bracket launches with HIP events; classes: names of the kernel classes
+        to time (all when None)."""
+        mask = 0xFFFFFFFF
+        if classes is not None:
+            names = [lib().ganmres_kernel_name(k).decode() for k in range(lib().ganmres_kernel_count())]
+            mask = 0
+            for c in classes:
+                mask |= 1 << names.index(c)
+        self._check(lib().ganmres_timing_select(self.h, mask))
         self._check(lib().ganmres_timing_enable(self.h, int(on)))
 
     def timing_reset(self):

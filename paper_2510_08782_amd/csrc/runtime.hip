@@ -202,6 +202,7 @@ class ProblemBase {
     virtual long long workspace_bytes() const = 0;
     // timing
     bool timing = false;
+    unsigned tmask = ~0u;  // kernel classes bracketed while timing
     double tms[KC_COUNT] = {};
     long long tcount[KC_COUNT] = {};
     virtual void timing_flush() = 0;
@@ -442,12 +443,18 @@ class Problem : public ProblemBase {
     }
 
     // -- timing -------------------------------------------------------------
+    // Only the selected classes are bracketed: every event pair costs the
+    // stream some microseconds, so a run that times one class leaves the
+    // others undisturbed.  The events skip the system-scope fence (the
+    // timestamps need no host-visible memory ordering).
+    bool tcur = false;
     void tbegin(int kind) {
-        if (!timing) return;
+        tcur = timing && ((tmask >> kind) & 1u);
+        if (!tcur) return;
         if (ev_used == ev_pool.size()) {
             hipEvent_t a, b2;
-            HIPCHK(hipEventCreate(&a));
-            HIPCHK(hipEventCreate(&b2));
+            HIPCHK(hipEventCreateWithFlags(&a, hipEventDisableSystemFence));
+            HIPCHK(hipEventCreateWithFlags(&b2, hipEventDisableSystemFence));
             ev_pool.push_back({a, b2});
             ev_kind.push_back(kind);
         }
@@ -455,7 +462,8 @@ class Problem : public ProblemBase {
         HIPCHK(hipEventRecord(ev_pool[ev_used].first, st));
     }
     void tend() {
-        if (!timing) return;
+        if (!tcur) return;
+        tcur = false;
         HIPCHK(hipEventRecord(ev_pool[ev_used].second, st));
         ++ev_used;
         if (ev_used >= 4096) timing_flush();
@@ -1964,6 +1972,14 @@ int ganmres_timing_enable(ganmres_handle* h, int on) {
     return guarded(h, [&] {
         if (!on) h->impl->timing_flush();
         h->impl->timing = on != 0;
+    });
+}
+
+int ganmres_timing_select(ganmres_handle* h, unsigned mask) {
+    if (!h) return GANMRES_EINVAL;
+    return guarded(h, [&] {
+        h->impl->timing_flush();
+        h->impl->tmask = mask;
     });
 }
 

@@ -108,14 +108,17 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
                              int accumulate, T* out, hipStream_t st);
 // Forward real-to-half-spectrum transform of `count` fields (count <= 3):
 // in[c] (real TI, N) -> out[c] (complex TC, NH), computed in precision TC.
+// skip_last: stop before the last complex pass (axis 3 - dim), which
+// launch_spec_fused then runs together with a spectral operator.
 template <typename TI, typename TC>
 hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* const* in,
-                       C2<TC>* const* out, int count, hipStream_t st);
+                       C2<TC>* const* out, int count, hipStream_t st, int skip_last = 0);
 // Inverse: spec[c] (overwritten) -> out[c] = scale * real(ifft) [+ add[c]]
+// skip_first: start after the first complex pass (run by launch_spec_fused).
 template <typename T>
 hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const* spec,
                         T* const* out, const T* const* add, double scale, int count,
-                        hipStream_t st);
+                        hipStream_t st, int skip_first = 0);
 
 struct SpecOpParams {
     int dim;
@@ -133,6 +136,17 @@ hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<doubl
 template <typename T>
 hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* const* gh,
                                C2<T>* const* sh, C2<T>* const* keep, hipStream_t st);
+// The last forward and the first inverse complex pass along axis 3 - dim fused
+// with a pointwise operator on the sp.dim spectra io[c] (in place; between
+// launch_rfft(..., skip_last = 1) and launch_irfft(..., skip_first = 1)):
+//   kSpecGrad:    io = alpha l_p vh + P io      (as launch_spec_gradient)
+//   kSpecPrecond: io = -P io / (alpha lbar_p)   (as launch_spec_precond; keep
+//                 nullable receives a copy of the spectrum)
+constexpr int kSpecGrad = 0, kSpecPrecond = 1;
+template <typename T>
+hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
+                             const SpecOpParams& sp, C2<T>* const* io, C2<double>* const* vh,
+                             C2<T>* const* keep, hipStream_t st);
 // sh[c] = sign (alpha lbar_p)^expo P gh[c] (P only when sp.leray; lbar_p: l_p
 // with its zero entry set to one); band_cut: the modes outside |k_i| <= n_i/2 - 1
 // are set to zero.

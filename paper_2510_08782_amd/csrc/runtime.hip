@@ -636,6 +636,7 @@ class Problem : public ProblemBase {
     }
     // copy the ingredients of J to the host behind an event (see J_from_host)
     void J_to_host() {
+        J_pending = false;
         const int n = reg_from_device ? R_REG + nb : nb;
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(ev_res, st));
@@ -758,6 +759,22 @@ class Problem : public ProblemBase {
     }
 
     double gradient(const void* v, void* g, bool reuse) override {
+        gradient_async(v, g, reuse);
+        return resolve_J();
+    }
+
+    // The gradient without waiting for J: J reaches the host behind ev_res and
+    // resolve_J() (or any later synchronisation followed by resolve_J) takes it
+    // up.  The solver calls this where J is already known (the accepted trial's
+    // forward solve is reused) or is needed only at the end of the step.
+    bool J_pending = false;
+    double resolve_J() {
+        if (!J_pending) return 0.0;
+        HIPCHK(hipEventSynchronize(ev_res));
+        J_pending = false;
+        return J_from_host(nullptr);
+    }
+    void gradient_async(const void* v, void* g, bool reuse) {
         if (reuse) {
             if (!fwd_valid || fwd_v != v)
                 throw Error(GANMRES_ESTATE, "reuse_forward without a kept forward solve for this v");
@@ -772,16 +789,17 @@ class Problem : public ProblemBase {
         // J reaches the host while the adjoint and the assembly run
         J_to_host();
         backward();
-        // assembly g = alpha L v + [P] b
+        // assembly g = alpha L v + [P] b (the operator fused with the last
+        // forward and the first inverse pass)
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
-        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st, 1); });
         run(KC_SPEC, [&] {
-            return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vh, wh, wh, st);
+            return launch_spec_fused<T>(dm, plans, kSpecGrad, specop(cfg.incompressible != 0), wh, vh,
+                                        nullptr, st);
         });
         T* gout[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
-        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / Nt, d, st); });
-        HIPCHK(hipEventSynchronize(ev_res));
-        return J_from_host(nullptr);
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / Nt, d, st, 1); });
+        J_pending = true;
     }
 
     double precond(const void* g, void* s) override {
@@ -796,17 +814,17 @@ class Problem : public ProblemBase {
     // v + rho s (dres[R_CROSS..], see launch_spec_cross)
     void precond_keep(const void* g, void* s, bool keep) {
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
-        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st); });
+        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st, 1); });
         run(KC_SPEC, [&] {
-            return launch_spec_precond<T>(dm, specop(cfg.incompressible != 0), wh, wh,
-                                          keep ? sk : nullptr, st);
+            return launch_spec_fused<T>(dm, plans, kSpecPrecond, specop(cfg.incompressible != 0), wh,
+                                        nullptr, keep ? sk : nullptr, st);
         });
         if (keep)
             run(KC_REDUCE, [&] {
                 return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
             });
         T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
-        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / Nt, d, st); });
+        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / Nt, d, st, 1); });
         run(KC_REDUCE, [&] {
             return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), vseg(), partial,
                                  dres + R_DOT, st);
@@ -1339,7 +1357,8 @@ class Problem : public ProblemBase {
         reg_s[0] = Rq;
         reg_from_device = false;
         std::swap(ring_v[0], qb);  // v^{k+1} = q, forward solve kept
-        gradient(rv(0), rg(0), true);
+        gradient_async(rv(0), rg(0), true);  // J(q) is the accepted trial's
+        J_pending = false;
         ++ngrad;
         info[0].step_kind = GANMRES_STEP_NEWTON;
         info[0].n_beta = its;
@@ -1606,19 +1625,21 @@ class Problem : public ProblemBase {
         HIPCHK(hipMemcpyAsync(hres + R_MAX, dres + R_MAX, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+        if (J_pending) resolve_J();  // the copy behind ev_res has run
+        const std::vector<double>& Jv = Jnew.empty() ? J_s : Jnew;
         const std::vector<double> ginf(hres + R_MAX, hres + R_MAX + nb);
         bool finite = true;
         for (int i = 0; i < nb; ++i) {
-            Jcur[i] = Jnew[i];
+            Jcur[i] = Jv[i];
             info[i].k = k;
-            info[i].J = Jnew[i];
+            info[i].J = Jv[i];
             info[i].J_q = Jq[i];
             info[i].ginf = ginf[i];
             info[i].g0inf = g0inf[i];
             info[i].rho = rho[i];
             info[i].n_grad = ngrad;
             info[i].stop = (ginf[i] <= p.eps_rel * g0inf[i]) || (k >= p.n_iter);
-            finite = finite && std::isfinite(Jnew[i]) && std::isfinite(ginf[i]);
+            finite = finite && std::isfinite(Jv[i]) && std::isfinite(ginf[i]);
         }
         if (!finite) throw Error(GANMRES_ENONFINITE, "non-finite objective or gradient");
     }
@@ -1657,7 +1678,9 @@ class Problem : public ProblemBase {
         const std::vector<double> rho = line_search(rv(cur), rg(cur), p, info, Jq);
         T* q = static_cast<T*>(qb->p);
         T* gq = static_cast<T*>(gqb->p);
-        gradient(q, gq, true);
+        // J(q) is the accepted trial's: no need to wait for it
+        gradient_async(q, gq, true);
+        J_pending = false;
         ++ngrad;
         // the free slot (not in the window)
         int slot = -1;
@@ -1681,8 +1704,7 @@ class Problem : public ProblemBase {
             std::vector<const T*> xs(wk + 1);
             for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
             combine(q, xs, beta, wk + 1, rv(slot));
-            gradient(rv(slot), rg(slot), false);
-            Jnew = J_s;
+            gradient_async(rv(slot), rg(slot), false);  // J taken up in finish_step
             ++ngrad;
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_NGMRES;
@@ -1730,7 +1752,8 @@ class Problem : public ProblemBase {
             // v^{k+1} = q: the trial buffer becomes the next iterate, and its
             // forward solve from the line search is reused
             std::swap(ring_v[nxt], qb);
-            gradient(rv(nxt), rg(nxt), true);
+            gradient_async(rv(nxt), rg(nxt), true);
+            J_pending = false;
             Jnew = J_s;
             for (int i = 0; i < nb; ++i) info[i].step_kind = GANMRES_STEP_FP;
         } else {
@@ -1741,8 +1764,7 @@ class Problem : public ProblemBase {
             std::vector<const T*> xs(wk);
             for (int i = 1; i <= wk; ++i) xs[i - 1] = aq(hist[hist.size() - i]);
             combine(q, xs, xi, wk, rv(nxt));
-            gradient(rv(nxt), rg(nxt), false);
-            Jnew = J_s;
+            gradient_async(rv(nxt), rg(nxt), false);  // J taken up in finish_step
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_AA;
                 info[i].n_beta = wk;

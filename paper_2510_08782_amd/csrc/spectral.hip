@@ -451,7 +451,10 @@ __device__ inline void leray_point(const KVec& kv, int dim, C2<T>* u) {
     double kc[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        kc[c] = c < dim ? kv.kt[comp_axis(dim, c)] : 0.0;
+        // component c lies along internal axis c (3-D) or c + 1 (2-D); both
+        // indices are constants here, so kt stays in registers
+        const double k3 = kv.kt[c], k2 = c + 1 < 3 ? kv.kt[c + 1 < 3 ? c + 1 : 2] : 0.0;
+        kc[c] = c < dim ? (dim == 3 ? k3 : k2) : 0.0;
         kk += kc[c] * kc[c];
     }
     if (kk == 0.0) return;
@@ -505,6 +508,108 @@ __global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, Sp
                 sh.spec[c][lin] = z;
                 if (has_keep) keep.spec[c][lin] = z;
             }
+    }
+}
+
+// The last forward and the first inverse pass of the complex transforms along
+// `axis`, with a spectral operator in between, on tiles of PC pencils holding
+// every component: per component the tile is transformed in LDS and kept in
+// registers, the operator (which couples the components through the Leray
+// projection) runs on the registers, and each component is transformed back
+// and stored in place.  The transforms and the operator are the ones of
+// c2c_axis_kernel and spec_gradient_kernel / spec_precond_kernel, so the
+// result is bitwise that of the three separate passes, without the two
+// round trips of the spectra through HBM between them.
+template <typename T, int LC, int OP>
+__global__ void __launch_bounds__(kFftThreads) c2c_spec_kernel(Dims dm, FftPlan<T> pl0, int axis,
+                                                               int pcshift, SpecOpParams sop,
+                                                               SpecPtrs<T> io, SpecPtrs<double> vh,
+                                                               SpecPtrs<T> keep, int has_keep) {
+    const int L = LC > 0 ? LC : pl0.L;
+    const int PC = 1 << pcshift;
+    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+    C2<T>* bufB = bufA + lpad_size(PC * L);
+    const FftPlan<T>& pl = pl0;
+    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+    const int nh = dm.n2h;
+    const long long npen = pencil_count(dm, axis, nh);
+    const long long stride = pencil_stride(dm, axis, nh);
+    const long long ntiles = (npen + PC - 1) >> pcshift;
+    const int pl_ = threadIdx.x & (PC - 1);
+    const int nitems = PC * L;
+    const int dim = sop.dim;
+    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const long long p = (tile << pcshift) + pl_;
+        const bool ok = p < npen;
+        const long long base = ok ? pencil_base(dm, axis, nh, p) : 0;
+        C2<T> R[3][kItems];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= dim) break;
+            const C2<T>* src = io.spec[c];
+#pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems)
+                    bufA[lpad(q)] = ok ? src[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+            }
+            __syncthreads();
+            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
+#pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                R[c][e] = q < nitems ? Z[lpad(q)] : cmk(T(0), T(0));
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            if (q >= nitems || !ok) continue;
+            const long long lin = base + (q >> pcshift) * stride;
+            const KVec kv = kvec(dm, lin);
+            C2<T> g[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[c] = c < dim ? R[c][e] : cmk(T(0), T(0));
+            if (sop.leray) leray_point(kv, dim, g);
+            if constexpr (OP == kSpecGrad) {
+                const double al = seg_alpha(sop, dm, lin) * ipow(kv.k2, sop.p);
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (c < dim) {
+                        const C2<double> z = vh.spec[c][lin];
+                        R[c][e] = cmk(T(al * z.x + double(g[c].x)), T(al * z.y + double(g[c].y)));
+                    }
+            } else {
+                double l = ipow(kv.k2, sop.p);
+                if (l == 0.0) l = 1.0;
+                const T f = T(-1.0 / (seg_alpha(sop, dm, lin) * l));
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+                    if (c < dim) {
+                        R[c][e] = cscale(g[c], f);
+                        if (has_keep) keep.spec[c][lin] = R[c][e];
+                    }
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            if (c >= dim) break;
+#pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems) bufA[lpad(q)] = R[c][e];
+            }
+            __syncthreads();
+            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+            C2<T>* dst = io.spec[c];
+#pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems && ok) dst[base + (q >> pcshift) * stride] = Z[lpad(q)];
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -712,7 +817,7 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
 
 template <typename TI, typename TC>
 hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* const* in,
-                       C2<TC>* const* out, int count, hipStream_t st) {
+                       C2<TC>* const* out, int count, hipStream_t st, int skip_last) {
     if (count < 1 || count > 3) return hipErrorInvalidValue;
     InPtrs<TI> ip{};
     SpecPtrs<TC> sp{};
@@ -731,7 +836,7 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
                 <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[2], sh, ip, sp);
         });
     }
-    for (int axis = 1; axis >= 3 - dm.dim; --axis) {
+    for (int axis = 1; axis >= 3 - dm.dim + (skip_last ? 1 : 0); --axis) {
         const int L = dm.n[axis];
         const long long npen = pencil_count(dm, axis, dm.n2h);
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen);
@@ -749,7 +854,7 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
 template <typename T>
 hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const* spec,
                         T* const* out, const T* const* add, double scale, int count,
-                        hipStream_t st) {
+                        hipStream_t st, int skip_first) {
     if (count < 1 || count > 3) return hipErrorInvalidValue;
     SpecPtrs<T> sp{};
     OutPtrs<T> op{};
@@ -758,7 +863,7 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         op.out[c] = out[c];
         op.add[c] = add ? add[c] : nullptr;
     }
-    for (int axis = 3 - dm.dim; axis <= 1; ++axis) {
+    for (int axis = 3 - dm.dim + (skip_first ? 1 : 0); axis <= 1; ++axis) {
         const int L = dm.n[axis];
         const long long npen = pencil_count(dm, axis, dm.n2h);
         const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
@@ -809,6 +914,40 @@ hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* co
         k.spec[c] = keep ? keep[c] : nullptr;
     }
     spec_precond_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, k, keep != nullptr);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
+                             const SpecOpParams& sp, C2<T>* const* io, C2<double>* const* vh,
+                             C2<T>* const* keep, hipStream_t st) {
+    if (sp.dim != dm.dim || (op != kSpecGrad && op != kSpecPrecond)) return hipErrorInvalidValue;
+    SpecPtrs<T> a{}, k{};
+    SpecPtrs<double> v{};
+    for (int c = 0; c < sp.dim; ++c) {
+        a.spec[c] = io[c];
+        k.spec[c] = keep ? keep[c] : nullptr;
+        v.spec[c] = vh ? vh[c] : nullptr;
+    }
+    if (op == kSpecGrad && !vh) return hipErrorInvalidValue;
+    const int axis = 3 - dm.dim;
+    const int L = dm.n[axis];
+    const long long npen = pencil_count(dm, axis, dm.n2h);
+    const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
+    const int PC = 1 << sh;
+    // one tile per workgroup: a tile carries every component, so the grid is a
+    // third of that of a single-field pass and needs all its workgroups
+    const unsigned g = strided_blocks((npen + PC - 1) / PC, 1);
+    with_length(L, [&](auto lc) {
+        if (op == kSpecGrad)
+            c2c_spec_kernel<T, decltype(lc)::value, kSpecGrad>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
+                    dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr);
+        else
+            c2c_spec_kernel<T, decltype(lc)::value, kSpecPrecond>
+                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
+                    dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr);
+    });
     return hipGetLastError();
 }
 
@@ -893,9 +1032,13 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
                                              const T* const*, const T* const*, const double*,     \
                                              int, int, T*, hipStream_t);                          \
     template hipError_t launch_rfft<T, T>(const Dims&, const SpectralPlans<T>&, const T* const*,  \
-                                          C2<T>* const*, int, hipStream_t);                       \
+                                          C2<T>* const*, int, hipStream_t, int);                  \
     template hipError_t launch_irfft<T>(const Dims&, const SpectralPlans<T>&, C2<T>* const*,      \
-                                        T* const*, const T* const*, double, int, hipStream_t);    \
+                                        T* const*, const T* const*, double, int, hipStream_t,     \
+                                        int);                                                     \
+    template hipError_t launch_spec_fused<T>(const Dims&, const SpectralPlans<T>&, int,           \
+                                             const SpecOpParams&, C2<T>* const*,                  \
+                                             C2<double>* const*, C2<T>* const*, hipStream_t);     \
     template hipError_t launch_spec_gradient<T>(const Dims&, const SpecOpParams&,                 \
                                                 C2<double>* const*, C2<T>* const*, C2<T>* const*, \
                                                 hipStream_t);                                     \
@@ -916,6 +1059,6 @@ GAN_INST(double)
 #undef GAN_INST
 template hipError_t launch_rfft<float, double>(const Dims&, const SpectralPlans<double>&,
                                                const float* const*, C2<double>* const*, int,
-                                               hipStream_t);
+                                               hipStream_t, int);
 
 }  // namespace gan

@@ -35,19 +35,24 @@ __device__ inline double block_reduce(double x, double* sh) {
     return r;
 }
 
-// Stage 2: res[q] = fold of partial[q*nb .. q*nb + nb) for q < nq (one block
-// of 1024 threads).
+// Stage 2: res[q] = fold of partial[q*nb .. q*nb + nb) for q < nq; workgroup
+// b of 1024 threads folds q = b, b + gridDim.x, ... (launch finish_blocks(nq)
+// of them, so that the quantities fold in parallel).
 template <bool MAX>
 __global__ void __launch_bounds__(1024) finish_kernel(const double* __restrict__ partial, int nb,
                                                       int nq, double* __restrict__ res) {
     __shared__ double sh[1024 / 64];
-    for (int q = 0; q < nq; ++q) {
+    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
         double x = MAX ? -INFINITY : 0.0;
         for (int i = threadIdx.x; i < nb; i += blockDim.x)
             x = MAX ? fmax(x, partial[(long long)q * nb + i]) : x + partial[(long long)q * nb + i];
         const double r = block_reduce<MAX>(x, sh);
         if (threadIdx.x == 0) res[q] = r;
     }
+}
+
+inline unsigned finish_blocks(long long nq) {
+    return (unsigned)(nq < 1 ? 1 : (nq > 4096 ? 4096 : nq));
 }
 
 }  // namespace gan

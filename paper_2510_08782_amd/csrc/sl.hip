@@ -852,7 +852,7 @@ hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, doub
     const int nb = reduction_blocks(dm.N);
     velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, s[0], s[1],
                                                     dm.dim == 3 ? s[2] : 0.0, partial);
-    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 1, res);
+    finish_kernel<true><<<finish_blocks(1), 1024, 0, st>>>(partial, nb, 1, res);
     return hipGetLastError();
 }
 

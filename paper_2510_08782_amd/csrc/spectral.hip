@@ -995,7 +995,7 @@ hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>*
     }
     const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 2);
     spec_cross_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, b, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, 2 * ns, res);
+    finish_kernel<false><<<finish_blocks(2 * ns), 1024, 0, st>>>(partial, nb, 2 * ns, res);
     return hipGetLastError();
 }
 
@@ -1023,7 +1023,7 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
     for (int c = 0; c < sp.dim; ++c) a.spec[c] = vh[c];
     const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 1);
     spec_regvalue_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, ns, res);
+    finish_kernel<false><<<finish_blocks(ns), 1024, 0, st>>>(partial, nb, ns, res);
     return hipGetLastError();
 }
 

@@ -89,8 +89,25 @@ struct VecList {
     const T* p[K];
 };
 
+// 16 bytes of T, moved with one load or store (elements W = 16 / sizeof(T))
+template <typename T>
+struct alignas(16) Vec16 {
+    static constexpr int W = 16 / (int)sizeof(T);
+    T v[W];
+};
+// rows of a segmented array can move as Vec16 when every row start is
+// 16-byte aligned
+template <typename T>
+bool vec16_rows(const Seg& g, std::initializer_list<const void*> ptrs) {
+    constexpr int W = 16 / (int)sizeof(T);
+    if (g.seglen % W != 0 || g.cstride % W != 0) return false;
+    for (const void* p : ptrs)
+        if (reinterpret_cast<unsigned long long>(p) & 15) return false;
+    return true;
+}
+
 template <typename T, int K>
-__global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg g,
+__global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg g, int vec,
                                                            double* __restrict__ partial) {
     __shared__ double sh[kRedThreads / 64];
     constexpr int NP = K * (K + 1) / 2;
@@ -98,19 +115,42 @@ __global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg
     double acc[NP];
 #pragma unroll
     for (int q = 0; q < NP; ++q) acc[q] = 0.0;
-    for (int c = 0; c < g.ncomp; ++c)
-        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
-             i += (long long)gridDim.x * blockDim.x) {
-            const long long e = seg_at(g, c, s, i);
-            double x[K];
+    auto add = [&](const double (&x)[K]) {
+        int q = 0;
 #pragma unroll
-            for (int a = 0; a < K; ++a) x[a] = static_cast<double>(vl.p[a][e]);
-            int q = 0;
+        for (int a = 0; a < K; ++a)
 #pragma unroll
-            for (int a = 0; a < K; ++a)
+            for (int b = a; b < K; ++b) acc[q++] += x[a] * x[b];
+    };
+    if (vec) {
+        constexpr int W = Vec16<T>::W;
+        const long long nv = g.seglen / W;
+        for (int c = 0; c < g.ncomp; ++c)
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv;
+                 i += (long long)gridDim.x * blockDim.x) {
+                const long long e = seg_at(g, c, s, 0) / W + i;
+                Vec16<T> xv[K];
 #pragma unroll
-                for (int b = a; b < K; ++b) acc[q++] += x[a] * x[b];
-        }
+                for (int a = 0; a < K; ++a) xv[a] = reinterpret_cast<const Vec16<T>*>(vl.p[a])[e];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    double x[K];
+#pragma unroll
+                    for (int a = 0; a < K; ++a) x[a] = static_cast<double>(xv[a].v[w]);
+                    add(x);
+                }
+            }
+    } else {
+        for (int c = 0; c < g.ncomp; ++c)
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+                 i += (long long)gridDim.x * blockDim.x) {
+                const long long e = seg_at(g, c, s, i);
+                double x[K];
+#pragma unroll
+                for (int a = 0; a < K; ++a) x[a] = static_cast<double>(vl.p[a][e]);
+                add(x);
+            }
+    }
 #pragma unroll
     for (int q = 0; q < NP; ++q) {
         const double r = block_reduce<false>(acc[q], sh);
@@ -149,7 +189,55 @@ struct CombineArgs {
     const T* x[kMaxCombine];
 };
 
-// out = q + sum_k coef[k nseg + s] (q - x_k) on segment s
+// out = q + sum_k coef[k nseg + s] (q - x_k) on segment s.  Windows of up to
+// 8 vectors take an unrolled kernel (coefficients and pointers in registers,
+// 16-byte moves); the general one serves the rest.
+template <typename T, int K>
+__global__ void combine_k_kernel(const T* __restrict__ q, CombineArgs<T> ca,
+                                 const double* __restrict__ coef, T* __restrict__ out, Seg g,
+                                 int vec) {
+    const int c = blockIdx.y / g.nseg, s = blockIdx.y % g.nseg;
+    const long long base = c * g.cstride + s * g.seglen;
+    T cs[K];
+    const T* xk[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        cs[k] = T(coef[k * g.nseg + s]);
+        xk[k] = ca.x[k] + base;
+    }
+    if (vec) {
+        constexpr int W = Vec16<T>::W;
+        const long long nv = g.seglen / W;
+        const Vec16<T>* qv = reinterpret_cast<const Vec16<T>*>(q + base);
+        Vec16<T>* ov = reinterpret_cast<Vec16<T>*>(out + base);
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv;
+             i += (long long)gridDim.x * blockDim.x) {
+            const Vec16<T> qi = qv[i];
+            Vec16<T> xv[K];
+#pragma unroll
+            for (int k = 0; k < K; ++k) xv[k] = reinterpret_cast<const Vec16<T>*>(xk[k])[i];
+            Vec16<T> acc;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                T a = qi.v[w];
+#pragma unroll
+                for (int k = 0; k < K; ++k) a += cs[k] * (qi.v[w] - xv[k].v[w]);
+                acc.v[w] = a;
+            }
+            ov[i] = acc;
+        }
+    } else {
+        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+             i += (long long)gridDim.x * blockDim.x) {
+            const T qi = q[base + i];
+            T acc = qi;
+#pragma unroll
+            for (int k = 0; k < K; ++k) acc += cs[k] * (qi - xk[k][i]);
+            out[base + i] = acc;
+        }
+    }
+}
+
 template <typename T>
 __global__ void combine_kernel(const T* __restrict__ q, CombineArgs<T> ca,
                                const double* __restrict__ coef, int K, T* __restrict__ out,
@@ -248,8 +336,10 @@ hipError_t gram_k(const T* const* vecs, const Seg& g, double* partial, double* r
     for (int a = 0; a < K; ++a) vl.p[a] = vecs[a];
     constexpr int NP = K * (K + 1) / 2;
     const int nb = seg_blocks(g, NP);
-    gram_kernel<T, K><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(vl, g, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, NP * g.nseg, res);
+    bool vec = vec16_rows<T>(g, {});
+    for (int a = 0; a < K; ++a) vec = vec && vec16_rows<T>(g, {vecs[a]});
+    gram_kernel<T, K><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(vl, g, vec ? 1 : 0, partial);
+    finish_kernel<false><<<finish_blocks(NP * g.nseg), 1024, 0, st>>>(partial, nb, NP * g.nseg, res);
     return hipGetLastError();
 }
 
@@ -272,7 +362,7 @@ hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, const Seg& g, doubl
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
     sumsq_diff_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, lam, g, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
+    finish_kernel<false><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
@@ -282,7 +372,7 @@ hipError_t launch_dot(const T* a, const T* b, const Seg& g, double* partial, dou
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
     dot_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, g, partial);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
+    finish_kernel<false><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
@@ -291,7 +381,7 @@ hipError_t launch_maxabs(const T* a, const Seg& g, double* partial, double* res,
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
     maxabs_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, partial);
-    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, g.nseg, res);
+    finish_kernel<true><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
 
@@ -324,8 +414,8 @@ hipError_t launch_det_stats(const T* const* J, const double* h, int d, const Seg
     a.d = d;
     const int nb = seg_blocks(g, 4);
     det_stats_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, det, partial);
-    finish_kernel<true><<<1, 1024, 0, st>>>(partial, nb, 2 * g.nseg, res);
-    finish_kernel<false><<<1, 1024, 0, st>>>(partial + (long long)2 * g.nseg * nb, nb, 2 * g.nseg,
+    finish_kernel<true><<<finish_blocks(2 * g.nseg), 1024, 0, st>>>(partial, nb, 2 * g.nseg, res);
+    finish_kernel<false><<<finish_blocks(2 * g.nseg), 1024, 0, st>>>(partial + (long long)2 * g.nseg * nb, nb, 2 * g.nseg,
                                              res + 2 * g.nseg);
     return hipGetLastError();
 }
@@ -354,8 +444,24 @@ hipError_t launch_combine(const T* q, const T* const* x, const double* coef, int
     if (K < 0 || K > kMaxCombine || !seg_valid(g)) return hipErrorInvalidValue;
     CombineArgs<T> ca;
     for (int k = 0; k < kMaxCombine; ++k) ca.x[k] = k < K ? x[k] : nullptr;
-    combine_kernel<T><<<dim3(row_blocks(g), g.ncomp * g.nseg), 256, 0, st>>>(q, ca, coef, K, out,
-                                                                           g);
+    const dim3 grid(row_blocks(g), g.ncomp * g.nseg);
+    bool vec = vec16_rows<T>(g, {q, out});
+    for (int k = 0; k < K; ++k) vec = vec && vec16_rows<T>(g, {x[k]});
+    const int v = vec ? 1 : 0;
+    switch (K) {
+#define GAN_COMBINE(KK) \
+    case KK: combine_k_kernel<T, KK><<<grid, 256, 0, st>>>(q, ca, coef, out, g, v); break;
+        GAN_COMBINE(1)
+        GAN_COMBINE(2)
+        GAN_COMBINE(3)
+        GAN_COMBINE(4)
+        GAN_COMBINE(5)
+        GAN_COMBINE(6)
+        GAN_COMBINE(7)
+        GAN_COMBINE(8)
+#undef GAN_COMBINE
+        default: combine_kernel<T><<<grid, 256, 0, st>>>(q, ca, coef, K, out, g);
+    }
     return hipGetLastError();
 }
 

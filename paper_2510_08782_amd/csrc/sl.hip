@@ -700,20 +700,39 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
 template <typename T>
 __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restrict__ v,
                                                                 long long N, int dim, double s0,
-                                                                double s1, double s2,
+                                                                double s1, double s2, int vec,
                                                                 double* __restrict__ partial) {
     __shared__ double sh[kThreads / 64];
     const double s[3] = {s0, s1, s2};
     double m = 0.0;
     bool bad = false;
+    constexpr int W = 16 / (int)sizeof(T);
+    struct alignas(16) V {
+        T x[W];
+    };
     for (int c = 0; c < dim; ++c) {
-        // max |v_c| in the field's type, scaled once (s_c > 0)
+        // max |v_c| in the field's type, scaled once (s_c > 0); with vec every
+        // thread moves 16 bytes at a time
         T mc = T(0);
-        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-             i += (long long)gridDim.x * blockDim.x) {
-            const T a = fabs(v[c * N + i]);
-            bad = bad || !(a == a);
-            mc = fmax(mc, a);
+        if (vec) {
+            const V* row = reinterpret_cast<const V*>(v + c * N);
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N / W;
+                 i += (long long)gridDim.x * blockDim.x) {
+                const V q = row[i];
+#pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const T a = fabs(q.x[w]);
+                    bad = bad || !(a == a);
+                    mc = fmax(mc, a);
+                }
+            }
+        } else {
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
+                 i += (long long)gridDim.x * blockDim.x) {
+                const T a = fabs(v[c * N + i]);
+                bad = bad || !(a == a);
+                mc = fmax(mc, a);
+            }
         }
         m = fmax(m, double(mc) * s[c]);
     }
@@ -850,8 +869,10 @@ template <typename T>
 hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, double* partial,
                                double* res, hipStream_t st) {
     const int nb = reduction_blocks(dm.N);
+    constexpr int W = 16 / (int)sizeof(T);
+    const int vec = (dm.N % W == 0 && (reinterpret_cast<unsigned long long>(v) & 15) == 0) ? 1 : 0;
     velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, s[0], s[1],
-                                                    dm.dim == 3 ? s[2] : 0.0, partial);
+                                                    dm.dim == 3 ? s[2] : 0.0, vec, partial);
     finish_kernel<true><<<finish_blocks(1), 1024, 0, st>>>(partial, nb, 1, res);
     return hipGetLastError();
 }

@@ -25,70 +25,6 @@ __device__ inline long long seg_at(const Seg& g, int c, int s, long long i) {
 }
 
 // Every reduction kernel runs gridDim.y = nseg rows of gridDim.x blocks; block
-// (x, s) strides over segment s and writes partial[(q nseg + s) gridDim.x + x]
-// for its quantity q.
-template <typename T>
-__global__ void __launch_bounds__(kRedThreads) sumsq_diff_kernel(const T* __restrict__ a,
-                                                                 const T* __restrict__ b,
-                                                                 T* __restrict__ lam, Seg g,
-                                                                 double* __restrict__ partial) {
-    __shared__ double sh[kRedThreads / 64];
-    const int s = blockIdx.y;
-    double acc = 0.0;
-    for (int c = 0; c < g.ncomp; ++c)
-        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
-             i += (long long)gridDim.x * blockDim.x) {
-            const long long e = seg_at(g, c, s, i);
-            const T d = b[e] - a[e];
-            if (lam) lam[e] = d;
-            const double dd = static_cast<double>(d);
-            acc += dd * dd;
-        }
-    const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kRedThreads) dot_kernel(const T* __restrict__ a,
-                                                          const T* __restrict__ b, Seg g,
-                                                          double* __restrict__ partial) {
-    __shared__ double sh[kRedThreads / 64];
-    const int s = blockIdx.y;
-    double acc = 0.0;
-    for (int c = 0; c < g.ncomp; ++c)
-        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
-             i += (long long)gridDim.x * blockDim.x) {
-            const long long e = seg_at(g, c, s, i);
-            acc += static_cast<double>(a[e]) * static_cast<double>(b[e]);
-        }
-    const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kRedThreads) maxabs_kernel(const T* __restrict__ a, Seg g,
-                                                             double* __restrict__ partial) {
-    __shared__ double sh[kRedThreads / 64];
-    const int s = blockIdx.y;
-    T m = T(0);
-    bool bad = false;
-    for (int c = 0; c < g.ncomp; ++c)
-        for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
-             i += (long long)gridDim.x * blockDim.x) {
-            const T x = fabs(a[seg_at(g, c, s, i)]);
-            bad = bad || !(x == x);
-            m = fmax(m, x);
-        }
-    // NaN and inf both count as inf
-    const double r = block_reduce<true>(bad ? INFINITY : static_cast<double>(m), sh);
-    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
-}
-
-template <typename T, int K>
-struct VecList {
-    const T* p[K];
-};
-
 // 16 bytes of T, moved with one load or store (elements W = 16 / sizeof(T))
 template <typename T>
 struct alignas(16) Vec16 {
@@ -105,6 +41,115 @@ bool vec16_rows(const Seg& g, std::initializer_list<const void*> ptrs) {
         if (reinterpret_cast<unsigned long long>(p) & 15) return false;
     return true;
 }
+
+// (x, s) strides over segment s and writes partial[(q nseg + s) gridDim.x + x]
+// for its quantity q.
+// f(e, w) on every element of segment s, element e of the array, w its
+// position in a 16-byte group; with vec the rows move as Vec16 (vec16_rows).
+// f gets the element's index and returns nothing; the loads are in f.
+template <typename T, typename F>
+__device__ inline void seg_for(const Seg& g, int s, bool vec, F&& f) {
+    if (vec) {
+        constexpr int W = Vec16<T>::W;
+        const long long nv = g.seglen / W;
+        for (int c = 0; c < g.ncomp; ++c)
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nv;
+                 i += (long long)gridDim.x * blockDim.x)
+                f(seg_at(g, c, s, 0) / W + i, true);
+    } else {
+        for (int c = 0; c < g.ncomp; ++c)
+            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < g.seglen;
+                 i += (long long)gridDim.x * blockDim.x)
+                f(seg_at(g, c, s, i), false);
+    }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) sumsq_diff_kernel(const T* __restrict__ a,
+                                                                 const T* __restrict__ b,
+                                                                 T* __restrict__ lam, Seg g,
+                                                                 int vec,
+                                                                 double* __restrict__ partial) {
+    __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
+    double acc = 0.0;
+    seg_for<T>(g, s, vec != 0, [&](long long e, bool v) {
+        if (v) {
+            const Vec16<T> av = reinterpret_cast<const Vec16<T>*>(a)[e];
+            const Vec16<T> bv = reinterpret_cast<const Vec16<T>*>(b)[e];
+            Vec16<T> dv;
+#pragma unroll
+            for (int w = 0; w < Vec16<T>::W; ++w) {
+                dv.v[w] = bv.v[w] - av.v[w];
+                const double dd = static_cast<double>(dv.v[w]);
+                acc += dd * dd;
+            }
+            if (lam) reinterpret_cast<Vec16<T>*>(lam)[e] = dv;
+        } else {
+            const T d = b[e] - a[e];
+            if (lam) lam[e] = d;
+            const double dd = static_cast<double>(d);
+            acc += dd * dd;
+        }
+    });
+    const double r = block_reduce<false>(acc, sh);
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) dot_kernel(const T* __restrict__ a,
+                                                          const T* __restrict__ b, Seg g, int vec,
+                                                          double* __restrict__ partial) {
+    __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
+    double acc = 0.0;
+    seg_for<T>(g, s, vec != 0, [&](long long e, bool v) {
+        if (v) {
+            const Vec16<T> av = reinterpret_cast<const Vec16<T>*>(a)[e];
+            const Vec16<T> bv = reinterpret_cast<const Vec16<T>*>(b)[e];
+#pragma unroll
+            for (int w = 0; w < Vec16<T>::W; ++w)
+                acc += static_cast<double>(av.v[w]) * static_cast<double>(bv.v[w]);
+        } else {
+            acc += static_cast<double>(a[e]) * static_cast<double>(b[e]);
+        }
+    });
+    const double r = block_reduce<false>(acc, sh);
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) maxabs_kernel(const T* __restrict__ a, Seg g,
+                                                             int vec,
+                                                             double* __restrict__ partial) {
+    __shared__ double sh[kRedThreads / 64];
+    const int s = blockIdx.y;
+    T m = T(0);
+    bool bad = false;
+    seg_for<T>(g, s, vec != 0, [&](long long e, bool v) {
+        if (v) {
+            const Vec16<T> av = reinterpret_cast<const Vec16<T>*>(a)[e];
+#pragma unroll
+            for (int w = 0; w < Vec16<T>::W; ++w) {
+                const T x = fabs(av.v[w]);
+                bad = bad || !(x == x);
+                m = fmax(m, x);
+            }
+        } else {
+            const T x = fabs(a[e]);
+            bad = bad || !(x == x);
+            m = fmax(m, x);
+        }
+    });
+    // NaN and inf both count as inf
+    const double r = block_reduce<true>(bad ? INFINITY : static_cast<double>(m), sh);
+    if (threadIdx.x == 0) partial[(long long)s * gridDim.x + blockIdx.x] = r;
+}
+
+template <typename T, int K>
+struct VecList {
+    const T* p[K];
+};
 
 template <typename T, int K>
 __global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg g, int vec,
@@ -361,7 +406,8 @@ hipError_t launch_sumsq_diff(const T* a, const T* b, T* lam, const Seg& g, doubl
                              double* res, hipStream_t st) {
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
-    sumsq_diff_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, lam, g, partial);
+    const int vec = vec16_rows<T>(g, {a, b, lam}) ? 1 : 0;
+    sumsq_diff_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, lam, g, vec, partial);
     finish_kernel<false><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
@@ -371,7 +417,8 @@ hipError_t launch_dot(const T* a, const T* b, const Seg& g, double* partial, dou
                       hipStream_t st) {
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
-    dot_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, g, partial);
+    const int vec = vec16_rows<T>(g, {a, b}) ? 1 : 0;
+    dot_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, b, g, vec, partial);
     finish_kernel<false><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }
@@ -380,7 +427,8 @@ template <typename T>
 hipError_t launch_maxabs(const T* a, const Seg& g, double* partial, double* res, hipStream_t st) {
     if (!seg_valid(g)) return hipErrorInvalidValue;
     const int nb = seg_blocks(g, 1);
-    maxabs_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, partial);
+    const int vec = vec16_rows<T>(g, {a}) ? 1 : 0;
+    maxabs_kernel<T><<<dim3(nb, g.nseg), kRedThreads, 0, st>>>(a, g, vec, partial);
     finish_kernel<true><<<finish_blocks(g.nseg), 1024, 0, st>>>(partial, nb, g.nseg, res);
     return hipGetLastError();
 }

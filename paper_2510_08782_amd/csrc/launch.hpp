@@ -25,18 +25,26 @@ int displacement_bound(double umax, int dim);
 template <typename T>
 hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, int spread, T* dX,
                                   T* dY, hipStream_t st);
+// Window table of a displacement field (per gather tile the floor range of its
+// displacements; window_table_ints ints): the first gather over a new field
+// passes table_write = 1 and records the windows it reduces, the following
+// ones pass 0 and start staging at once.  Nullable (no table).
+template <typename T>
+long long window_table_ints(const Dims& dm);
 // out = [fac *] I[src](i + disp)
 template <typename T>
 hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int spread,
-                          T* out, hipStream_t st);
+                          T* out, hipStream_t st, int* table = nullptr, int table_write = 0);
 // out = add + I[src](i + disp)   (one step of the deformation map)
 template <typename T>
 hipError_t launch_sl_step_add(const Dims& dm, const T* src, const T* disp, const T* add,
-                              int spread, T* out, hipStream_t st);
+                              int spread, T* out, hipStream_t st, int* table = nullptr,
+                              int table_write = 0);
 // out = 1 + sgn h_t/2 (I[delta](i+disp) + delta) + h_t^2/2 delta I[delta](i+disp)
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, int spread, T* out, hipStream_t st);
+                                double sgn, int spread, T* out, hipStream_t st,
+                                int* table = nullptr, int table_write = 0);
 
 // ---- reductions and vector kernels (vec.hip) -------------------------------
 // Arrays are segmented: a batch of nseg independent problems stacked along the

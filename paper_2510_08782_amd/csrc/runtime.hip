@@ -224,6 +224,15 @@ class Problem : public ProblemBase {
     std::vector<std::unique_ptr<DevBuf>> bufs;
     DevBuf twbuf[3], twbuf64[3];
     T *m0, *m1, *dX, *dY, *delta, *cfac, *bfac, *b, *tmp;
+    // window tables of dX and dY: the first gather over a new field records
+    // its windows (tw() gives that gather table_write = 1), the later ones read them
+    int *tabX = nullptr, *tabY = nullptr;
+    bool tabX_ok = false, tabY_ok = false;
+    static int tw(bool& ok) {
+        const int w = ok ? 0 : 1;
+        ok = true;
+        return w;
+    }
     // State / adjoint storage.  Full mode (checkpoint_every == 1): every m^j
     // and lam^j.  Checkpoint mode: m^j at the checkpoint times 0, c, 2c, ...,
     // nt only, c-1 fields for the interior states of a segment (the forward
@@ -379,6 +388,13 @@ class Problem : public ProblemBase {
         }
         dX = alloc_T(d * N);
         dY = alloc_T(d * N);
+        for (int** tab : {&tabX, &tabY}) {
+            const long long ints = window_table_ints<T>(dm);
+            bufs.emplace_back(new DevBuf);
+            bufs.back()->alloc(sizeof(int) * (size_t)ints);
+            ws_bytes += sizeof(int) * ints;
+            *tab = static_cast<int*>(bufs.back()->p);
+        }
         const bool compressible = !c.incompressible;
         delta = compressible ? alloc_T(N) : nullptr;
         cfac = (compressible && c.model == GANMRES_CONTINUITY) ? alloc_T(N) : nullptr;
@@ -573,14 +589,16 @@ class Problem : public ProblemBase {
             return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, ubound, dX,
                                              needY ? dY : nullptr, st);
         });
+        tabX_ok = false;
+        if (needY) tabY_ok = false;
         y_valid = needY;
         if (cfac)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dX, ht, -1.0, dbound, cfac, st);
+                return launch_source_factor<T>(dm, delta, dX, ht, -1.0, dbound, cfac, st, tabX, tw(tabX_ok));
             });
         if (bfac && needY)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st);
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st, tabY, tw(tabY_ok));
             });
     }
 
@@ -591,9 +609,10 @@ class Problem : public ProblemBase {
             return launch_characteristics<T>(dm, static_cast<const T*>(v), cscale, ubound, nullptr,
                                              dY, st);
         });
+        tabY_ok = false;
         if (bfac)
             run(KC_FACTOR, [&] {
-                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st);
+                return launch_source_factor<T>(dm, delta, dY, ht, +1.0, dbound, bfac, st, tabY, tw(tabY_ok));
             });
         y_valid = true;
     }
@@ -615,7 +634,7 @@ class Problem : public ProblemBase {
     void forward() {
         for (int j = 0; j < cfg.nt; ++j)
             run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, mstate(j), dX, cfac, dbound, mstate(j + 1), st);
+                return launch_sl_step<T>(dm, mstate(j), dX, cfac, dbound, mstate(j + 1), st, tabX, tw(tabX_ok));
             });
     }
 
@@ -703,7 +722,7 @@ class Problem : public ProblemBase {
             for (int j = nt - 1; j >= 0; --j)
                 run(KC_SL, [&] {
                     return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
-                                             lamh + (long long)j * N, st);
+                                             lamh + (long long)j * N, st, tabY, tw(tabY_ok));
                 });
             std::vector<const T*> mp(nt + 1), lp(nt + 1);
             std::vector<double> w(nt + 1);
@@ -728,7 +747,7 @@ class Problem : public ProblemBase {
                 mp[i] = mint[i - 1];
                 T* src = mp[i - 1];
                 T* dst = mp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, dbound, dst, st); });
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, dbound, dst, st, tabX, tw(tabX_ok)); });
             }
             std::vector<int> idx;
             for (int i = 0; i < (int)lpool.size(); ++i)
@@ -740,7 +759,7 @@ class Problem : public ProblemBase {
                 if (i == 0) newtop = idx[q];
                 T* src = lp[i + 1];
                 T* dst = lp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, dbound, dst, st); });
+                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, dbound, dst, st, tabY, tw(tabY_ok)); });
             }
             // time level j0 belongs to the previous segment, except t = 0
             const int i0 = sgi == 0 ? 0 : 1;
@@ -935,7 +954,7 @@ class Problem : public ProblemBase {
         run(KC_VEC, [&] { return launch_axpy<T>(f, mhalf.data(), f, ga, sseg(), st); });
         for (int j = 0; j < nt; ++j) {
             run(KC_SL, [&] {
-                return launch_sl_step_add<T>(dm, ga, dX, f + (long long)(j + 1) * N, dbound, gb, st);
+                return launch_sl_step_add<T>(dm, ga, dX, f + (long long)(j + 1) * N, dbound, gb, st, tabX, tw(tabX_ok));
             });
             std::swap(ga, gb);
         }
@@ -947,7 +966,7 @@ class Problem : public ProblemBase {
         for (int j = nt - 1; j >= 0; --j)
             run(KC_SL, [&] {
                 return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
-                                         lamh + (long long)j * N, st);
+                                         lamh + (long long)j * N, st, tabY, tw(tabY_ok));
             });
         std::vector<const T*> mp(nt + 1), lp(nt + 1);
         std::vector<double> w(nt + 1);
@@ -1392,7 +1411,7 @@ class Problem : public ProblemBase {
             for (int a = 0; a < d; ++a)
                 run(KC_SL, [&] {
                     return launch_sl_step_add<T>(dm, comp(Da, a), dX, comp(dX, a), dbound,
-                                                 comp(Db, a), st);
+                                                 comp(Db, a), st, tabX, tw(tabX_ok));
                 });
             std::swap(Da, Db);
         }

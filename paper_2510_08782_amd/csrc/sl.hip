@@ -184,10 +184,30 @@ __device__ inline int disp_floor(T d) {
     return static_cast<int>(floor(clamp_disp(d)));
 }
 
+// The window of a tile whose displacement floors span [m[a], M[a]] per axis
+// (x, y, z order).
+template <class C>
+__device__ inline Window window_from(const int (&m_)[3], const int (&M_)[3]) {
+    Window w;
+    const int T3[3] = {C::TX, C::TY, C::TZ};
+    w.lds = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        int m = m_[a], M = M_[a];
+        if (a == 2 && C::DIM == 2) m = M = 0;  // slice axis: no interpolation
+        const int spread = M - m;
+        w.lds = w.lds && spread <= C::S && m >= -(1 << 20) && M <= (1 << 20);
+        w.lo[a] = m;
+        w.ext[a] = (a == 2 && C::DIM == 2) ? 1 : T3[a] + spread + 3;
+    }
+    return w;
+}
+
 // Block-wide window from per-thread floor ranges fmn/fmx (x, y, z order).
 // red: 6 ints per wave of LDS.  Contains a barrier.
 template <class C>
-__device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], int* red) {
+__device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], int* red,
+                                     int* entry = nullptr) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -199,24 +219,22 @@ __device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], i
         }
     }
     __syncthreads();
-    Window w;
-    const int T3[3] = {C::TX, C::TY, C::TZ};
-    w.lds = true;
+    int m[3], M[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        int m = red[a], M = red[3 + a];
+        m[a] = red[a];
+        M[a] = red[3 + a];
 #pragma unroll
         for (int q = 1; q < kThreads / 64; ++q) {
-            m = min(m, red[q * 6 + a]);
-            M = max(M, red[q * 6 + 3 + a]);
+            m[a] = min(m[a], red[q * 6 + a]);
+            M[a] = max(M[a], red[q * 6 + 3 + a]);
         }
-        if (a == 2 && C::DIM == 2) m = M = 0;  // slice axis: no interpolation
-        const int spread = M - m;
-        w.lds = w.lds && spread <= C::S && m >= -(1 << 20) && M <= (1 << 20);
-        w.lo[a] = m;
-        w.ext[a] = (a == 2 && C::DIM == 2) ? 1 : T3[a] + spread + 3;
     }
-    return w;
+    if (entry && threadIdx.x < 6) {
+        const int i = threadIdx.x;
+        entry[i] = i == 0 ? m[0] : i == 1 ? m[1] : i == 2 ? m[2] : i == 3 ? M[0] : i == 4 ? M[1] : M[2];
+    }
+    return window_from<C>(m, M);
 }
 
 // Stage src over the window of the tile with origin (x0, y0, z0).
@@ -380,6 +398,7 @@ __device__ inline typename C::T gather_lds(const typename C::T* lds, const Windo
 // [k ceil(T/8), (k+1) ceil(T/8)): a slab whose halos are mostly read from
 // the same L2 instead of once per XCD.
 constexpr int kXcds = 8;
+constexpr int kWinInts = 8;  // ints per tile in a window table
 
 template <class C>
 __host__ __device__ inline int tile_count(const Dims& dm) {
@@ -392,14 +411,14 @@ __host__ __device__ inline int tile_count(const Dims& dm) {
 // Tile origin of this block and the local coordinates of the thread's k-th point.
 template <class C>
 struct PointMap {
-    int x0, y0, z0;
+    int x0, y0, z0, t;
     bool valid;
     __device__ PointMap(const Dims& dm) {
         const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
         const int nty = (dm.n[1] + C::TY - 1) / C::TY;
         const int T = tile_count<C>(dm);
         const int per = (T + kXcds - 1) / kXcds;
-        const int t = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+        t = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
         valid = t < T;
         x0 = (t % ntx) * C::TX;
         y0 = ((t / ntx) % nty) * C::TY;
@@ -444,11 +463,17 @@ __device__ inline T step_epilogue(T r, const T* __restrict__ src, const T* __res
 // kernels, so that the LDS path does not carry the direct gather's registers;
 // the second is launched only when the spread bound allows a tile to
 // exceed the window.
+//
+// table (nullable): the window table of disp.  With table_write = 0 it holds
+// every tile's floor ranges, the window is known at once, and the staging of
+// the source is in flight while the displacements load.  With table_write = 1
+// (the first gather over a new field) the LDS kernel reduces its windows as
+// without a table and records them there.
 template <class C, int EPI, bool LDS>
 __global__ void __launch_bounds__(kThreads) sl_step_kernel(
     Dims dm, const typename C::T* __restrict__ src, const typename C::T* __restrict__ disp,
     const typename C::T* __restrict__ fac, typename C::T ht, typename C::T sgn,
-    typename C::T* __restrict__ out) {
+    typename C::T* __restrict__ out, int* __restrict__ table, int table_write) {
     using T = typename C::T;
     constexpr int DIM = C::DIM;
     extern __shared__ double2 sl_smem[];
@@ -456,6 +481,15 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
     __shared__ int red[6 * (kThreads / 64)];
     const PointMap<C> pm(dm);
     if (!pm.valid) return;
+    Window win{};
+    const bool use_table = table && !table_write;
+    if (use_table) {
+        const int* e = table + (long long)pm.t * kWinInts;
+        const int m[3] = {e[0], e[1], e[2]}, M[3] = {e[3], e[4], e[5]};
+        win = window_from<C>(m, M);
+        if (win.lds != LDS) return;
+        if constexpr (LDS) stage<C, false>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
+    }
     const long long N = dm.N;
     // displacements of the thread's points and their floor ranges
     T d0[C::PTS], d1[C::PTS], d2[C::PTS];
@@ -479,17 +513,25 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
                 d1[k] = disp[lin[k]];
                 d2[k] = disp[N + lin[k]];
             }
-            const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
+            if (!use_table) {
+                const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
 #pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                fmn[q] = min(fmn[q], f[q]);
-                fmx[q] = max(fmx[q], f[q]);
+                for (int q = 0; q < 3; ++q) {
+                    fmn[q] = min(fmn[q], f[q]);
+                    fmx[q] = max(fmx[q], f[q]);
+                }
             }
         }
     }
-    const Window win = tile_window<C>(fmn, fmx, red);
-    if (win.lds != LDS) return;
-    if constexpr (LDS) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
+    if (!use_table) {
+        win = tile_window<C>(fmn, fmx, red,
+                             (LDS && table) ? table + (long long)pm.t * kWinInts : nullptr);
+        if (win.lds != LDS) return;
+        if constexpr (LDS) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
+    } else if constexpr (LDS) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         if (!in[k]) continue;
@@ -807,32 +849,36 @@ void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int spre
 template <class C, int EPI>
 void step_kernels(const Dims& dm, const typename C::T* src, const typename C::T* disp,
                   const typename C::T* fac, double ht, double sgn, int spread,
-                  typename C::T* out, hipStream_t st) {
+                  typename C::T* out, int* table, int table_write, hipStream_t st) {
     using T = typename C::T;
     sl_step_kernel<C, EPI, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-        dm, src, disp, fac, T(ht), T(sgn), out);
+        dm, src, disp, fac, T(ht), T(sgn), out, table, table_write);
+    // the direct-gather kernel reads the table only once it is complete
     if (spread > C::S)
         sl_step_kernel<C, EPI, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
-            dm, src, disp, fac, T(ht), T(sgn), out);
+            dm, src, disp, fac, T(ht), T(sgn), out, table, 0);
 }
 
 template <class C>
 void step_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
-                 const typename C::T* fac, int spread, typename C::T* out, hipStream_t st) {
-    if (fac) step_kernels<C, 1>(dm, src, disp, fac, 0.0, 0.0, spread, out, st);
-    else step_kernels<C, 0>(dm, src, disp, fac, 0.0, 0.0, spread, out, st);
+                 const typename C::T* fac, int spread, typename C::T* out, int* table,
+                 int tw, hipStream_t st) {
+    if (fac) step_kernels<C, 1>(dm, src, disp, fac, 0.0, 0.0, spread, out, table, tw, st);
+    else step_kernels<C, 0>(dm, src, disp, fac, 0.0, 0.0, spread, out, table, tw, st);
 }
 
 template <class C>
 void add_launch(const Dims& dm, const typename C::T* src, const typename C::T* disp,
-                const typename C::T* add, int spread, typename C::T* out, hipStream_t st) {
-    step_kernels<C, 3>(dm, src, disp, add, 0.0, 0.0, spread, out, st);
+                const typename C::T* add, int spread, typename C::T* out, int* table, int tw,
+                hipStream_t st) {
+    step_kernels<C, 3>(dm, src, disp, add, 0.0, 0.0, spread, out, table, tw, st);
 }
 
 template <class C>
 void factor_launch(const Dims& dm, const typename C::T* delta, const typename C::T* disp,
-                   double ht, double sgn, int spread, typename C::T* out, hipStream_t st) {
-    step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, spread, out, st);
+                   double ht, double sgn, int spread, typename C::T* out, int* table, int tw,
+                   hipStream_t st) {
+    step_kernels<C, 2>(dm, delta, disp, nullptr, ht, sgn, spread, out, table, tw, st);
 }
 
 // Calls f(Tile<...>{}) with the variant chosen for `spread`.
@@ -888,30 +934,45 @@ hipError_t launch_characteristics(const Dims& dm, const T* v, const double* s, i
 
 template <typename T>
 hipError_t launch_sl_step(const Dims& dm, const T* src, const T* disp, const T* fac, int spread,
-                          T* out, hipStream_t st) {
+                          T* out, hipStream_t st, int* table, int table_write) {
     dispatch_tile<T>(dm, spread, [&](auto tile) {
-        step_launch<decltype(tile)>(dm, src, disp, fac, spread, out, st);
+        step_launch<decltype(tile)>(dm, src, disp, fac, spread, out, table, table_write, st);
     });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_sl_step_add(const Dims& dm, const T* src, const T* disp, const T* add,
-                              int spread, T* out, hipStream_t st) {
+                              int spread, T* out, hipStream_t st, int* table, int table_write) {
     dispatch_tile<T>(dm, spread, [&](auto tile) {
-        add_launch<decltype(tile)>(dm, src, disp, add, spread, out, st);
+        add_launch<decltype(tile)>(dm, src, disp, add, spread, out, table, table_write, st);
     });
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, double ht,
-                                double sgn, int spread, T* out, hipStream_t st) {
+                                double sgn, int spread, T* out, hipStream_t st, int* table,
+                                int table_write) {
     dispatch_tile<T>(dm, spread, [&](auto tile) {
-        factor_launch<decltype(tile)>(dm, delta, disp, ht, sgn, spread, out, st);
+        factor_launch<decltype(tile)>(dm, delta, disp, ht, sgn, spread, out, table, table_write, st);
     });
     return hipGetLastError();
 }
+
+// The tile geometry does not depend on the window capacity: one table serves
+// every variant.
+template <typename T>
+long long window_table_ints(const Dims& dm) {
+    long long n = 0;
+    dispatch_tile<T>(dm, 0, [&](auto tile) {
+        using C = decltype(tile);
+        n = (long long)tile_count<C>(dm) * kWinInts;
+    });
+    return n;
+}
+
+
 
 #define GAN_INST(T)                                                                               \
     template hipError_t launch_velocity_max<T>(const Dims&, const T*, const double*, double*,     \
@@ -919,11 +980,12 @@ hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, d
     template hipError_t launch_characteristics<T>(const Dims&, const T*, const double*, int, T*,  \
                                                   T*, hipStream_t);                               \
     template hipError_t launch_sl_step<T>(const Dims&, const T*, const T*, const T*, int, T*,     \
-                                          hipStream_t);                                           \
+                                          hipStream_t, int*, int);                                \
     template hipError_t launch_sl_step_add<T>(const Dims&, const T*, const T*, const T*, int, T*, \
-                                              hipStream_t);                                       \
+                                              hipStream_t, int*, int);                            \
     template hipError_t launch_source_factor<T>(const Dims&, const T*, const T*, double, double,  \
-                                                int, T*, hipStream_t);
+                                                int, T*, hipStream_t, int*, int);                 \
+    template long long window_table_ints<T>(const Dims&);
 GAN_INST(float)
 GAN_INST(double)
 #undef GAN_INST

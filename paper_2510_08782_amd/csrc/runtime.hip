@@ -223,7 +223,7 @@ class Problem : public ProblemBase {
     SpectralPlans<double> plans64{};  // the FP64 spectrum of v (regulariser)
     std::vector<std::unique_ptr<DevBuf>> bufs;
     DevBuf twbuf[3], twbuf64[3];
-    T *m0, *m1, *dX, *dY, *delta, *cfac, *bfac, *b, *tmp;
+    T *m0, *m1, *dX, *dY, *delta, *cfac, *bfac, *b;
     // window tables of dX and dY: the first gather over a new field records
     // its windows (tw() gives that gather table_write = 1), the later ones read them
     int *tabX = nullptr, *tabY = nullptr;
@@ -400,7 +400,6 @@ class Problem : public ProblemBase {
         cfac = (compressible && c.model == GANMRES_CONTINUITY) ? alloc_T(N) : nullptr;
         bfac = (compressible && c.model == GANMRES_ADVECTION) ? alloc_T(N) : nullptr;
         b = alloc_T(d * N);
-        tmp = alloc_T(d * N);
         for (int cc = 0; cc < 3; ++cc) {
             vh[cc] = nullptr;
             if (cc < d) {
@@ -979,20 +978,23 @@ class Problem : public ProblemBase {
         // assembly: alpha L vt + [P] b (FP64 spectrum of vt, as for v); data_only:
         // [P] b alone (the data term of the two-level preconditioner)
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
-        run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
+        T* hout[3] = {comp(out, 0), comp(out, 1), d == 3 ? comp(out, 2) : nullptr};
         if (data_only) {
+            run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st); });
             run(KC_SPEC, [&] {
                 return launch_spec_pow<T>(dm, specop(cfg.incompressible != 0), wh, wh, 0.0, 1.0, 0, st);
             });
+            run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, hout, nullptr, 1.0 / Nt, d, st); });
         } else {
             const T* vin[3] = {comp(vt, 0), comp(vt, 1), d == 3 ? comp(vt, 2) : nullptr};
             run(KC_RFFT, [&] { return launch_rfft<T, double>(dm, plans64, vin, vth, d, st); });
+            run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st, 1); });
             run(KC_SPEC, [&] {
-                return launch_spec_gradient<T>(dm, specop(cfg.incompressible != 0), vth, wh, wh, st);
+                return launch_spec_fused<T>(dm, plans, kSpecGrad, specop(cfg.incompressible != 0), wh,
+                                            vth, nullptr, st);
             });
+            run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, hout, nullptr, 1.0 / Nt, d, st, 1); });
         }
-        T* hout[3] = {comp(out, 0), comp(out, 1), d == 3 ? comp(out, 2) : nullptr};
-        run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, hout, nullptr, 1.0 / Nt, d, st); });
     }
 
     // ---- preconditioners of the Newton step (Appendix A) ---------------------

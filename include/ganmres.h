@@ -167,8 +167,9 @@ int ganmres_eval_objective(ganmres_handle* h, const void* v, int keep_history,
  * lam(1) = m1 - m(1)), b = -int pi grad lam dt (continuity), and b replaced
  * by its Leray projection when incompressible.  g is the L2 representer: a
  * grid function with dJ(v)[d] ~ <g, d>_h.  v, g: device velocities (may not
- * alias).  reuse_forward = 1: the caller asserts that the last
- * ganmres_eval_objective(keep_history = 1) was for this same v, and its forward
+ * alias).  reuse_forward = 1: the caller asserts that the last evaluation on
+ * the handle (ganmres_eval_objective(keep_history = 1) or
+ * ganmres_eval_gradient) was for this same v, unchanged since, and its forward
  * solve is reused.  J: host, nullable.
  * Errors: GANMRES_ESTATE (reuse without a kept history), GANMRES_ENONFINITE. */
 int ganmres_eval_gradient(ganmres_handle* h, const void* v, void* g,

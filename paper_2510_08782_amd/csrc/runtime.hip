@@ -454,6 +454,7 @@ class Problem : public ProblemBase {
         for (auto& r : aa_r) s += r->bytes;
         for (auto& r : aa_q) s += r->bytes;
         if (qb) s += qb->bytes + gqb->bytes + sb->bytes;
+        if (coarse) s += coarse->workspace_bytes();  // the two-level preconditioner's grid
         return s;
     }
 

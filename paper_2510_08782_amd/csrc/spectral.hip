@@ -237,20 +237,52 @@ __global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<
     const long long rows = (long long)dm.n[0] * dm.n[1];
     const long long q0 = (long long)blockIdx.x * 2 * PC;
     const int nitems = 2 * PC * L;
-    T vals[kItems];
-#pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        const int r = q / L, i = q - r * L;
-        vals[e] = (q < nitems && q0 + r < rows) ? T(in[(q0 + r) * L + i]) : T(0);
-    }
     T* flat = reinterpret_cast<T*>(bufA);
+    // rows of a compiled length that is a multiple of 16 bytes move with
+    // 16-byte loads, WI consecutive elements per thread
+    constexpr int WI = 16 / (int)sizeof(TI);
+    if (LC > 0 && LC % WI == 0 && (reinterpret_cast<unsigned long long>(in) & 15) == 0) {
+        struct alignas(16) V {
+            TI x[WI];
+        };
+        V vals[kItems / WI];
 #pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        if (q < nitems) {
+        for (int e = 0; e < kItems / WI; ++e) {
+            const int q = (threadIdx.x + e * kFftThreads) * WI;
             const int r = q / L, i = q - r * L;
-            flat[2 * lpad((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+            if (q < nitems && q0 + r < rows) {
+                vals[e] = *reinterpret_cast<const V*>(in + (q0 + r) * L + i);
+            } else {
+#pragma unroll
+                for (int w = 0; w < WI; ++w) vals[e].x[w] = TI(0);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kItems / WI; ++e) {
+            const int q = (threadIdx.x + e * kFftThreads) * WI;
+            if (q < nitems) {
+                const int r = q / L, i = q - r * L;
+#pragma unroll
+                for (int w = 0; w < WI; ++w)
+                    flat[2 * lpad(((i + w) << pcshift) + (r & (PC - 1))) + (r >> pcshift)] =
+                        T(vals[e].x[w]);
+            }
+        }
+    } else {
+        T vals[kItems];
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            const int r = q / L, i = q - r * L;
+            vals[e] = (q < nitems && q0 + r < rows) ? T(in[(q0 + r) * L + i]) : T(0);
+        }
+#pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            if (q < nitems) {
+                const int r = q / L, i = q - r * L;
+                flat[2 * lpad((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+            }
         }
     }
     __syncthreads();
@@ -388,6 +420,40 @@ __global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<
     }
     __syncthreads();
     const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+    constexpr int W = 16 / (int)sizeof(T);
+    if (LC > 0 && LC % W == 0 && (reinterpret_cast<unsigned long long>(out) & 15) == 0 &&
+        (reinterpret_cast<unsigned long long>(add) & 15) == 0) {
+        // 16-byte stores (and loads of add), W consecutive elements per thread
+        struct alignas(16) V {
+            T x[W];
+        };
+        V addv[kItems / W];
+#pragma unroll
+        for (int e = 0; e < kItems / W; ++e) {
+            const int q = (threadIdx.x + e * kFftThreads) * W;
+            const int r = q / L, i = q - r * L;
+            if (add && q < 2 * nitems && q0 + r < rows) {
+                addv[e] = *reinterpret_cast<const V*>(add + (q0 + r) * L + i);
+            } else {
+#pragma unroll
+                for (int w = 0; w < W; ++w) addv[e].x[w] = T(0);
+            }
+        }
+#pragma unroll
+        for (int e = 0; e < kItems / W; ++e) {
+            const int q = (threadIdx.x + e * kFftThreads) * W;
+            const int r = q / L, i = q - r * L;
+            if (q >= 2 * nitems || q0 + r >= rows) continue;
+            V o;
+#pragma unroll
+            for (int w = 0; w < W; ++w) {
+                const C2<T> z = Z[lpad(((i + w) << pcshift) + (r & (PC - 1)))];
+                o.x[w] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e].x[w];
+            }
+            *reinterpret_cast<V*>(out + (q0 + r) * L + i) = o;
+        }
+        return;
+    }
     T addv[kItems];
 #pragma unroll
     for (int e = 0; e < kItems; ++e) {

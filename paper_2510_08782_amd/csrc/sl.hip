@@ -119,7 +119,7 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
 // 3-D: threads (32 x 8), each owns TZ points along z.  2-D: threads (64 x 4),
 // each owns 8 points along y (tile 64 x 32).  S is the capacity of the staged
 // region: up to S cells of spread of the displacement floors per axis.
-template <typename T_, int DIM_, int S_, int TZ_ = (sizeof(T_) == 4 ? 8 : 4)>
+template <typename T_, int DIM_, int S_, int TZ_ = (sizeof(T_) == 4 ? 2 : 4)>
 struct Tile;
 template <typename T_, int S_, int TZ_>
 struct Tile<T_, 3, S_, TZ_> {
@@ -503,23 +503,27 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
         const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
         in[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
         lin[k] = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
-        d0[k] = d1[k] = d2[k] = T(0);
-        if (in[k]) {
-            if constexpr (DIM == 3) {
-                d0[k] = disp[lin[k]];
-                d1[k] = disp[N + lin[k]];
-                d2[k] = disp[2 * N + lin[k]];
-            } else {
-                d1[k] = disp[lin[k]];
-                d2[k] = disp[N + lin[k]];
-            }
-            if (!use_table) {
-                const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
+        // every lane loads (a point outside the grid reads element 0), so
+        // that the loads of all points are in flight together
+        const long long lc = in[k] ? lin[k] : 0;
+        if constexpr (DIM == 3) {
+            d0[k] = disp[lc];
+            d1[k] = disp[N + lc];
+            d2[k] = disp[2 * N + lc];
+        } else {
+            d0[k] = T(0);
+            d1[k] = disp[lc];
+            d2[k] = disp[N + lc];
+        }
+    }
+    if (!use_table) {
 #pragma unroll
-                for (int q = 0; q < 3; ++q) {
-                    fmn[q] = min(fmn[q], f[q]);
-                    fmx[q] = max(fmx[q], f[q]);
-                }
+        for (int k = 0; k < C::PTS; ++k) {
+            const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+                fmn[q] = in[k] ? min(fmn[q], f[q]) : fmn[q];
+                fmx[q] = in[k] ? max(fmx[q], f[q]) : fmx[q];
             }
         }
     }
@@ -566,82 +570,66 @@ __global__ void __launch_bounds__(kThreads) characteristics_kernel(
     if (!pm.valid) return;
     const long long N = dm.N;
     const T s[3] = {s0, s1, s2};
-    // floor ranges of the predictor displacements -u (state) / +u (adjoint)
-    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    // u at the thread's points, all loads in flight together (a point
+    // outside the grid reads element 0 and is masked)
+    T u[C::PTS][DIM];
+    bool inp[C::PTS];
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         int lx, ly, lz;
         pm.local(k, lx, ly, lz);
         const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
-        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+        inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+        const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) u[k][c] = v[c * N + lc];
+    }
+    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+#pragma unroll
+    for (int k = 0; k < C::PTS; ++k) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const T e = v[c * N + lin] * s[c];
+            u[k][c] = inp[k] ? u[k][c] * s[c] : T(0);
             const int q = DIM - 1 - c;  // axis slot: x, y, z
             if (DOX) {
-                const int f = disp_floor(-e);
-                fmn[q] = min(fmn[q], f);
-                fmx[q] = max(fmx[q], f);
+                const int f = disp_floor(-u[k][c]);
+                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
             }
             if (DOY) {
-                const int f = disp_floor(e);
-                fmn[q] = min(fmn[q], f);
-                fmx[q] = max(fmx[q], f);
+                const int f = disp_floor(u[k][c]);
+                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
             }
         }
     }
     const Window win = tile_window<C>(fmn, fmx, red);
     if (win.lds != LDS) return;
-    // u at the thread's k-th point (zero outside the grid)
-    auto load_u = [&](int k, T* u, long long& lin, bool& in) {
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        in = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
-        lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] = (in && q < DIM) ? v[q * N + lin] * s[q] : T(0);
-    };
     for (int c = 0; c < DIM; ++c) {
         const T* vc = v + c * N;
         if constexpr (LDS) {
             if (c > 0) __syncthreads();
             stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0, win);
         }
-        // the next point's u is loaded while the current one interpolates
-        T un[3];
-        long long linn;
-        bool inn;
-        load_u(0, un, linn, inn);
-#pragma unroll 1
+#pragma unroll
         for (int k = 0; k < C::PTS; ++k) {
-            const T u[3] = {un[0], un[1], un[2]};
-            const long long lin = linn;
-            const bool in = inn;
-            if (k + 1 < C::PTS) load_u(k + 1, un, linn, inn);
-            if (!in) continue;
+            if (!inp[k]) continue;
             int lx, ly, lz;
             pm.local(k, lx, ly, lz);
             const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-            T e0 = T(0), e1, e2;
-            if constexpr (DIM == 3) {
-                e0 = u[0];
-                e1 = u[1];
-                e2 = u[2];
-            } else {
-                e1 = u[0];
-                e2 = u[1];
-            }
+            const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+            const T e0 = DIM == 3 ? u[k][0] : T(0), e1 = DIM == 3 ? u[k][1] : u[k][0];
+            const T e2 = DIM == 3 ? u[k][2] : u[k][1];
             if (DOX) {
                 const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, -e0, -e1, -e2)
                                  : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
-                dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * iv);
+                dX[c * N + lin] = T(-0.5) * (u[k][c] + s[c] * iv);
             }
             if (DOY) {
                 const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, e0, e1, e2)
                                  : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
-                dY[c * N + lin] = T(0.5) * (u[c] + s[c] * iv);
+                dY[c * N + lin] = T(0.5) * (u[k][c] + s[c] * iv);
             }
         }
     }
@@ -667,26 +655,35 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
     const long long N = dm.N;
     const T s[3] = {s0, s1, s2};
     int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    // every lane loads (a point outside the grid reads element 0), so that
+    // the loads of all points are in flight together
+    T ev[C::PTS][DIM];
+    bool inp[C::PTS];
 #pragma unroll
     for (int k = 0; k < C::PTS; ++k) {
         int lx, ly, lz;
         pm.local(k, lx, ly, lz);
         const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        if (i2 >= dm.n[2] || i1 >= dm.n[1] || i0 >= dm.n[0]) continue;
-        const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+        inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+        const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) ev[k][c] = v[c * N + lc];
+    }
+#pragma unroll
+    for (int k = 0; k < C::PTS; ++k) {
 #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const T e = v[c * N + lin] * s[c];
-            const int q = DIM - 1 - c;
+            const T e = ev[k][c] * s[c];
+            const int q = DIM - 1 - c;  // axis slot: x, y, z
             if (DOX) {
                 const int f = disp_floor(-e);
-                fmn[q] = min(fmn[q], f);
-                fmx[q] = max(fmx[q], f);
+                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
             }
             if (DOY) {
                 const int f = disp_floor(e);
-                fmn[q] = min(fmn[q], f);
-                fmx[q] = max(fmx[q], f);
+                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
             }
         }
     }
@@ -699,28 +696,16 @@ __global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
         else
             stage<C, true>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
     }
-    auto load_u = [&](int k, T* u, long long& lin, bool& in) {
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        in = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
-        lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
 #pragma unroll
-        for (int q = 0; q < 3; ++q) u[q] = (in && q < DIM) ? v[q * N + lin] * s[q] : T(0);
-    };
-    T un[3];
-    long long linn;
-    bool inn;
-    load_u(0, un, linn, inn);
-#pragma unroll 1
     for (int k = 0; k < C::PTS; ++k) {
-        const T u[3] = {un[0], un[1], un[2]};
-        const long long lin = linn;
-        const bool in = inn;
-        if (k + 1 < C::PTS) load_u(k + 1, un, linn, inn);
-        if (!in) continue;
+        if (!inp[k]) continue;
         int lx, ly, lz;
         pm.local(k, lx, ly, lz);
+        const long long lin =
+            ((long long)(pm.z0 + lz) * dm.n[1] + (pm.y0 + ly)) * dm.n[2] + (pm.x0 + lx);
+        T u[DIM];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) u[c] = ev[k][c] * s[c];
         const T e0 = DIM == 3 ? u[0] : T(0), e1 = DIM == 3 ? u[1] : u[0];
         const T e2 = DIM == 3 ? u[2] : u[1];
         if (DOX) {

@@ -264,8 +264,8 @@ def main():
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
-                                   "(see the sharding notes in DESIGN.md)"}))
+        print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is designed, not built)"}))
         sys.exit(2)
 
     import numpy as np

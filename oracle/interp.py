@@ -2,7 +2,7 @@
 
 The semi-Lagrangian scheme of Sec. 2.2 evaluates the transported field at
 departure points that are off the grid.  The paper does not name the kernel;
-this build uses a cubic (4-point) Lagrange polynomial per axis, i.e. the
+this implementation uses a cubic (4-point) Lagrange polynomial per axis, i.e. the
 tricubic (3-D) / bicubic (2-D) tensor-product stencil, without prefiltering.
 
 Points are given in index space: xi_j is measured in cells along axis j, so the

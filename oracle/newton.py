@@ -15,7 +15,7 @@ regularisation operator as preconditioner ("ireg").
                        body force when incompressible)
 
 Readings (the paper points to its earlier work for these):
-  * lt(1) = -mt(1): the increment of lam(1) = m1 - m(1) under this build's sign
+  * lt(1) = -mt(1): the increment of lam(1) = m1 - m(1) under this implementation's sign
     reading of the adjoint final value (the printed mt(1) belongs to the
     opposite sign convention);
   * the incremental state is integrated along the state's characteristics with

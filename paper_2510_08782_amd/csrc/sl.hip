@@ -812,10 +812,11 @@ void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int spre
                typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
     // both directions: all components staged at once (one staging and one
-    // stencil per point serve X and Y), on 3-D tiles of 4 planes, where that
-    // fits; a single direction stages one component at a time, which keeps
-    // more workgroups per CU
-    using CA = Tile<T, C::DIM, C::S, 4>;
+    // stencil per point serve X and Y), on the gather's tiles (2 planes in
+    // FP32, which fit three workgroups per CU, 4 in FP64), where that fits;
+    // a single direction stages one component at a time, which keeps more
+    // workgroups per CU
+    using CA = C;
     if constexpr (C::DIM * tile_lds_bytes<CA>() <= kMaxLds / 2) {
         if (dX && dY) {
             char_all_launch<CA, true, true>(dm, v, s, spread, dX, dY, st);

@@ -243,7 +243,7 @@ def c4_throughput(torch, gan, synth):
                                          "rel_grad_max": max(i.ginf / i.g0inf for i in infos)}
         B.reset()
     dt = time.perf_counter() - t0
-    ngrad += len(wls)  # g(v^0) of every problem
+    # n_grad of each first step already counts g(v^0)
     for _, B in batches:
         B.close()
     return {"problems": len(wls), "iterations_each": params.n_iter, "seconds": round(dt, 4),

@@ -106,6 +106,9 @@ typedef struct {
     int n_grad;            /* gradient evaluations in this call                 */
     int n_beta;            /* number of valid entries in beta (Newton steps:
                               the CG iterations taken)                          */
+    int lsq_fallback;      /* 1 when this step's least-squares solve fell back
+                              from Cholesky to the pseudo-inverse (rank-deficient
+                              or ill-conditioned window, see ganmres_lsq)       */
     double J;              /* J(v^{k+1})                                        */
     double J_q;            /* J(q(v^k))                                         */
     double ginf;           /* ||g(v^{k+1})||_inf                                */
@@ -252,6 +255,19 @@ int ganmres_hessian_matvec(ganmres_handle* h, const void* v, const void* vt, voi
  * handle's adjoint fields.
  * Errors: GANMRES_EINVAL. */
 int ganmres_newton_precond(ganmres_handle* h, int which, const void* v, const void* r, void* z);
+
+/* The least-squares problem of the NGMRES mixing step (Alg. 1, and Alg. 3's
+ * NGMRES iterations): beta = argmin || r + sum_i beta_i (r - g_i) ||_2 over
+ * the columns of the window, from the Gram matrix of u = [r, g_0, ..,
+ * g_{K-2}] (G: host, K x K row major, symmetric, finite; 2 <= K <= 66).
+ * With M_ij = (r - g_i).(r - g_j) the normal equations M beta = -(|r|^2 -
+ * r.g_i) are solved by Cholesky; when it breaks down or the squared pivot
+ * ratio is below 1e-12 (the window is rank-deficient or nearly so; Sec. 2.3
+ * leaves the treatment of rank deficiency open), by the eigen pseudo-inverse
+ * with cutoff 1e-12 lambda_max.  This is the host solve ganmres_step uses.
+ * beta: host, K - 1 entries.  fallback: host, nullable, set to 1 when the
+ * pseudo-inverse was used.  Errors: GANMRES_EINVAL, GANMRES_ELSQ. */
+int ganmres_lsq(int K, const double* G, double* beta, int* fallback);
 
 /* Forget the solver state (k, rho, history); the next ganmres_step starts a
  * new solve from the v it is given. */

@@ -59,6 +59,7 @@ class SolverParams(ctypes.Structure):
 class StepInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int), ("step_kind", ctypes.c_int), ("stop", ctypes.c_int),
                 ("n_trials", ctypes.c_int), ("n_grad", ctypes.c_int), ("n_beta", ctypes.c_int),
+                ("lsq_fallback", ctypes.c_int),
                 ("J", ctypes.c_double), ("J_q", ctypes.c_double), ("ginf", ctypes.c_double),
                 ("g0inf", ctypes.c_double), ("rho", ctypes.c_double),
                 ("beta", ctypes.c_double * (MAX_WINDOW + 1))]
@@ -92,6 +93,7 @@ def lib():
     L.ganmres_apply_precond.argtypes = [vp, vp, vp, dp]
     L.ganmres_step.argtypes = [vp, ctypes.POINTER(SolverParams), vp, ctypes.POINTER(StepInfo)]
     L.ganmres_solver_reset.argtypes = [vp]
+    L.ganmres_lsq.argtypes = [ip, dp, dp, ctypes.POINTER(ctypes.c_int)]
     L.ganmres_get_field.argtypes = [vp, ip, ip, vp]
     L.ganmres_timing_enable.argtypes = [vp, ip]
     L.ganmres_timing_reset.argtypes = [vp]
@@ -104,6 +106,21 @@ def lib():
     L.ganmres_workspace_bytes.restype = ctypes.c_longlong
     _lib = L
     return L
+
+
+def lsq(G):
+    """beta and the fallback flag of the library's host least-squares solve for
+    the Gram matrix G (K x K) of [r, g_0, .., g_{K-2}] (see ganmres_lsq)."""
+    import numpy as np
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    K = G.shape[0]
+    beta = (ctypes.c_double * (K - 1))()
+    fb = ctypes.c_int()
+    rc = lib().ganmres_lsq(K, G.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), beta,
+                           ctypes.byref(fb))
+    if rc != 0:
+        raise GanmresError(rc, "ganmres_lsq")
+    return np.array(beta[:]), bool(fb.value)
 
 
 def header_symbols():

@@ -52,6 +52,8 @@ hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, d
 // c * cstride + s * seglen + i: component c < ncomp, segment s < nseg,
 // i < seglen.  A single problem is one segment.
 constexpr int kMaxSeg = 64;
+constexpr int kMaxGram = 66;                          // window of 64 plus two vectors
+constexpr long long kGramPartialDoubles = 256 * 1024;
 struct Seg {
     int nseg;
     int ncomp;
@@ -75,8 +77,10 @@ hipError_t launch_dot(const T* a, const T* b, const Seg& g, double* partial, dou
 // max |a| with NaN mapped to +inf
 template <typename T>
 hipError_t launch_maxabs(const T* a, const Seg& g, double* partial, double* res, hipStream_t st);
-// Gram matrix of K <= 8 vectors per segment: res[q nseg + s] holds packed
-// upper-triangle entry q (pairs (a, b >= a) in row order) of segment s
+// Gram matrix of K <= kMaxGram vectors per segment: res[q nseg + s] holds
+// packed upper-triangle entry q (pairs (a, b >= a) in row order) of segment
+// s.  K > 8 needs a partials buffer of kGramPartialDoubles doubles and
+// K (K + 1) / 2 * nseg <= kGramPartialDoubles.
 template <typename T>
 hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partial, double* res,
                        hipStream_t st);

@@ -166,8 +166,10 @@ static void eigen_pinv_solve(int n, const std::vector<double>& M, const std::vec
     }
 }
 
-// beta from the packed upper-triangle Gram of u = [r, g_0, ..., g_{n-1}].
-static std::vector<double> lsq_from_gram(int K, const std::vector<double>& G) {
+// beta from the Gram matrix (K x K, row major) of u = [r, g_0, ..., g_{K-2}];
+// *fallback (nullable) is set when the pseudo-inverse had to be used.
+static std::vector<double> lsq_from_gram(int K, const std::vector<double>& G,
+                                         bool* fallback = nullptr) {
     const int n = K - 1;
     const double Grr = G[0];
     std::vector<double> M(n * n), y(n), x;
@@ -179,7 +181,9 @@ static std::vector<double> lsq_from_gram(int K, const std::vector<double>& G) {
             M[i * n + j] = Grr - Gri - Grj + G[(i + 1) * K + (j + 1)];
         }
     }
-    if (!cholesky_solve(n, M, y, x)) eigen_pinv_solve(n, M, y, x);
+    const bool chol = cholesky_solve(n, M, y, x);
+    if (!chol) eigen_pinv_solve(n, M, y, x);
+    if (fallback) *fallback = !chol;
     return x;
 }
 
@@ -269,7 +273,7 @@ class Problem : public ProblemBase {
     double* hres = nullptr;  // pinned host results
     double* hup = nullptr;   // pinned staging of host -> device tables
     // slots of the device / host result buffers (per-problem values from s)
-    static constexpr int kRes = 8192;
+    static constexpr int kRes = 2048 + kMaxGram * (kMaxGram + 1) / 2 * kMaxSeg;
     static constexpr int R_MIS = 0, R_REG = 256, R_DOT = 512, R_SMAX = 768, R_CROSS = 1024,
                          R_MAX = 1280, R_UMAX = 1536, R_GRAM = 2048;
     long long ws_bytes = 0;
@@ -413,7 +417,7 @@ class Problem : public ProblemBase {
         }
         {
             bufs.emplace_back(new DevBuf);
-            bufs.back()->alloc(sizeof(double) * 64 * 1024);
+            bufs.back()->alloc(sizeof(double) * kGramPartialDoubles);
             partial = static_cast<double*>(bufs.back()->p);
             bufs.emplace_back(new DevBuf);
             bufs.back()->alloc(sizeof(double) * kRes);
@@ -1590,36 +1594,29 @@ class Problem : public ProblemBase {
     }
 
     // least-squares coefficients per problem from the FP64 Gram matrices of
-    // vecs[0..K): beta[i * K .. ] is the solution of problem i (K <= 8 vectors
-    // in one reduction; more in pairwise dots)
+    // vecs[0..K) (one reduction over the K vectors and one fetch):
+    // beta[i * (K-1) ..] is the solution of problem i; lsq_fb[i] records
+    // whether its solve fell back to the pseudo-inverse
+    std::vector<char> lsq_fb;
     std::vector<double> gram_lsq(const std::vector<const T*>& vecs) {
         const int K = (int)vecs.size();
         const int np = K * (K + 1) / 2;
         std::vector<double> G(np * nb);
-        if (K <= 8) {
-            run(KC_REDUCE, [&] {
-                return launch_gram<T>(vecs.data(), K, vseg(), partial, dres + R_GRAM, st);
-            });
-            const double* r = fetch(R_GRAM, np * nb);
-            for (int x = 0; x < np * nb; ++x) G[x] = r[x];
-        } else {
-            int qi = 0;
-            for (int a = 0; a < K; ++a)
-                for (int bb = a; bb < K; ++bb, ++qi) {
-                    run(KC_REDUCE, [&] {
-                        return launch_dot<T>(vecs[a], vecs[bb], vseg(), partial, dres + R_DOT, st);
-                    });
-                    const double* r = fetch(R_DOT, nb);
-                    for (int i = 0; i < nb; ++i) G[qi * nb + i] = r[i];
-                }
-        }
+        run(KC_REDUCE, [&] {
+            return launch_gram<T>(vecs.data(), K, vseg(), partial, dres + R_GRAM, st);
+        });
+        const double* r = fetch(R_GRAM, np * nb);
+        for (int x = 0; x < np * nb; ++x) G[x] = r[x];
         std::vector<double> beta;
         std::vector<double> Gi(K * K);
+        lsq_fb.assign(nb, 0);
         for (int i = 0; i < nb; ++i) {
             int qi = 0;
             for (int a = 0; a < K; ++a)
                 for (int bb = a; bb < K; ++bb, ++qi) Gi[a * K + bb] = Gi[bb * K + a] = G[qi * nb + i];
-            const std::vector<double> bi = lsq_from_gram(K, Gi);
+            bool fb = false;
+            const std::vector<double> bi = lsq_from_gram(K, Gi, &fb);
+            lsq_fb[i] = fb ? 1 : 0;
             for (double x : bi)
                 if (!std::isfinite(x)) throw Error(GANMRES_ELSQ, "non-finite least-squares coefficients");
             beta.insert(beta.end(), bi.begin(), bi.end());
@@ -1731,6 +1728,7 @@ class Problem : public ProblemBase {
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_NGMRES;
                 info[i].n_beta = wk + 1;
+                info[i].lsq_fallback = lsq_fb[i];
                 for (int j = 0; j <= wk && j <= GANMRES_MAX_WINDOW; ++j)
                     info[i].beta[j] = beta[i * (wk + 1) + j];
             }
@@ -1790,6 +1788,7 @@ class Problem : public ProblemBase {
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_AA;
                 info[i].n_beta = wk;
+                info[i].lsq_fallback = lsq_fb[i];
                 for (int j = 0; j < wk && j <= GANMRES_MAX_WINDOW; ++j) info[i].beta[j] = xi[i * wk + j];
             }
         }
@@ -1840,6 +1839,7 @@ static int guarded(ganmres_handle* h, F&& f) {
 // the Python binding mirrors these layouts
 static_assert(sizeof(ganmres_config) == 48, "ganmres_config layout");
 static_assert(sizeof(ganmres_solver_params) == 72, "ganmres_solver_params layout");
+static_assert(sizeof(ganmres_step_info) == 592, "ganmres_step_info layout");
 
 static int create_impl(const ganmres_config* cfg, int count, const double* alpha, const void* m0,
                        const void* m1, void* stream, ganmres_handle** out) {
@@ -1904,6 +1904,26 @@ int ganmres_batch_count(const ganmres_handle* h) { return h ? h->impl->count() :
 int ganmres_batch_values(ganmres_handle* h, double* J, double* mismatch) {
     if (!h || (!J && !mismatch)) return GANMRES_EINVAL;
     return guarded(h, [&] { h->impl->values(J, mismatch); });
+}
+
+int ganmres_lsq(int K, const double* G, double* beta, int* fallback) {
+    if (K < 2 || K > gan::kMaxGram || !G || !beta) return GANMRES_EINVAL;
+    try {
+        std::vector<double> Gv(G, G + (size_t)K * K);
+        for (int a = 0; a < K; ++a)
+            for (int b = 0; b < K; ++b)
+                if (!std::isfinite(Gv[a * K + b]) || Gv[a * K + b] != Gv[b * K + a]) return GANMRES_EINVAL;
+        bool fb = false;
+        const std::vector<double> x = gan::lsq_from_gram(K, Gv, &fb);
+        for (int i = 0; i < K - 1; ++i) {
+            if (!std::isfinite(x[i])) return GANMRES_ELSQ;
+            beta[i] = x[i];
+        }
+        if (fallback) *fallback = fb ? 1 : 0;
+        return GANMRES_OK;
+    } catch (...) {
+        return GANMRES_ENOMEM;
+    }
 }
 
 int ganmres_destroy(ganmres_handle* h) {

@@ -769,14 +769,16 @@ __global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restr
 }
 
 // Variant choice from a bound on the spread of the displacement floors over
-// the field (cells; a displacement bound B gives floor(B) + ceil(B)): the
-// smallest capacity that covers it; beyond the largest, the largest runs and
-// only tiles whose own spread exceeds it gather from global memory.
+// the field (cells; a displacement bound B gives floor(B) + ceil(B), which is
+// odd unless B is an integer): the smallest capacity that covers it; beyond
+// the largest, the largest runs and only tiles whose own spread exceeds it
+// gather from global memory.  FP32 3-D: 2, 3 or 8 (a bound of 4 would need B
+// to be exactly 2); FP64 3-D: 2, 3 or 4, the largest that fits the LDS.
 template <typename T, int DIM>
 int pick_capacity(int spread) {
     if (DIM == 2) return spread <= 8 ? 8 : 16;
     if (sizeof(T) == 8) return spread <= 2 ? 2 : (spread <= 3 ? 3 : 4);
-    return spread <= 2 ? 2 : (spread <= 3 ? 3 : (spread <= 4 ? 4 : 8));
+    return spread <= 2 ? 2 : (spread <= 3 ? 3 : 8);
 }
 
 template <class C, bool DOX, bool DOY>
@@ -812,10 +814,12 @@ void char_dirs(const Dims& dm, const typename C::T* v, const double* s, int spre
                typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
     // both directions: all components staged at once (one staging and one
-    // stencil per point serve X and Y), on the gather's tiles (2 planes in
-    // FP32, which fit three workgroups per CU, 4 in FP64), where that fits;
-    // a single direction stages one component at a time, which keeps more
-    // workgroups per CU
+    // stencil per point serve X and Y), on the gather's tiles, where the d
+    // windows take at most half the LDS: in 2-D, and in 3-D FP32 with
+    // capacities 2 and 3 (2 planes per tile, three workgroups per CU).  3-D
+    // FP64 (4 planes per tile) and capacity 8 never fit and stage one
+    // component at a time, as a single direction always does (that keeps
+    // more workgroups per CU)
     using CA = C;
     if constexpr (C::DIM * tile_lds_bytes<CA>() <= kMaxLds / 2) {
         if (dX && dY) {
@@ -875,7 +879,6 @@ void dispatch_tile(const Dims& dm, int spread, F&& f) {
         if (c == 2) f(Tile<T, 3, 2>{});
         else if (c == 3) f(Tile<T, 3, 3>{});
         else if constexpr (sizeof(T) == 8) f(Tile<T, 3, 4>{});
-        else if (c == 4) f(Tile<T, 3, 4>{});
         else f(Tile<T, 3, 8>{});
     } else {
         if (pick_capacity<T, 2>(spread) == 8) f(Tile<T, 2, 8>{});

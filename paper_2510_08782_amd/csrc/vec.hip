@@ -151,6 +151,92 @@ struct VecList {
     const T* p[K];
 };
 
+// Gram matrix of K > 8 vectors (up to the largest window plus two) in one
+// pass over the data.  A block stages a chunk of kGramE elements of every
+// vector in LDS (as FP64), then its threads form the chunk's products in 4 x 4
+// tiles of vector pairs: the upper triangle of the padded K x K matrix has
+// ntiles tiles, each owned by S = blockDim / ntiles threads that split the
+// chunk's elements.  After the last chunk the S partial tiles are folded in
+// a fixed order, so the result does not depend on timing.
+constexpr int kGramE = 128;
+constexpr long long kGramPartialCap = kGramPartialDoubles;
+template <typename T>
+struct PtrList {
+    const T* p[kMaxGram];
+};
+
+__host__ __device__ inline int packed_pair(int a, int b, int K) { return a * K - a * (a - 1) / 2 + (b - a); }
+
+template <typename T>
+__global__ void __launch_bounds__(kRedThreads) gram_big_kernel(PtrList<T> pl, int K, Seg g,
+                                                               double* __restrict__ partial) {
+    extern __shared__ double gsm[];  // max(Kp kGramE, kRedThreads 16) doubles
+    const int s = blockIdx.y;
+    const int nt = (K + 3) / 4, Kp = 4 * nt;
+    const int ntiles = nt * (nt + 1) / 2;
+    const int S = kRedThreads / ntiles;
+    const int t = threadIdx.x;
+    const bool active = t < ntiles * S;
+    const int tile = active ? t / S : 0, slice = active ? t % S : 0;
+    int ta = 0, rem = tile;
+    while (rem >= nt - ta) {
+        rem -= nt - ta;
+        ++ta;
+    }
+    const int tb = ta + rem;
+    double acc[4][4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] = 0.0;
+    for (int i = t; i < (Kp - K) * kGramE; i += blockDim.x) gsm[K * kGramE + i] = 0.0;
+    const long long nch = (g.seglen + kGramE - 1) / kGramE;
+    const long long total = nch * g.ncomp;
+    for (long long ch = blockIdx.x; ch < total; ch += gridDim.x) {
+        const int c = static_cast<int>(ch / nch);
+        const long long i0 = (ch % nch) * kGramE;
+        const long long base = seg_at(g, c, s, i0);
+        const int len = static_cast<int>(min(static_cast<long long>(kGramE), g.seglen - i0));
+        __syncthreads();  // the previous chunk has been read
+        for (int idx = t; idx < K * kGramE; idx += blockDim.x) {
+            const int a = idx / kGramE, e = idx % kGramE;
+            gsm[idx] = e < len ? static_cast<double>(pl.p[a][base + e]) : 0.0;
+        }
+        __syncthreads();
+        if (active) {
+            const double* xa = gsm + 4 * ta * kGramE;
+            const double* xb = gsm + 4 * tb * kGramE;
+            for (int e = slice; e < len; e += S) {
+                double x[4], y[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    x[r] = xa[r * kGramE + e];
+                    y[r] = xb[r * kGramE + e];
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+#pragma unroll
+                    for (int c2 = 0; c2 < 4; ++c2) acc[r][c2] = fma(x[r], y[c2], acc[r][c2]);
+            }
+        }
+    }
+    __syncthreads();
+    if (active) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) gsm[t * 16 + q] = acc[q / 4][q % 4];
+    }
+    __syncthreads();
+    if (active && slice == 0) {
+        for (int q = 0; q < 16; ++q) {
+            double sum = gsm[(tile * S) * 16 + q];
+            for (int j = 1; j < S; ++j) sum += gsm[(tile * S + j) * 16 + q];
+            const int a = 4 * ta + q / 4, b = 4 * tb + q % 4;
+            if (a < K && b < K && a <= b)
+                partial[((long long)packed_pair(a, b, K) * gridDim.y + s) * gridDim.x + blockIdx.x] = sum;
+        }
+    }
+}
+
 template <typename T, int K>
 __global__ void __launch_bounds__(kRedThreads) gram_kernel(VecList<T, K> vl, Seg g, int vec,
                                                            double* __restrict__ partial) {
@@ -448,8 +534,24 @@ hipError_t launch_gram(const T* const* vecs, int K, const Seg& g, double* partia
         case 6: return gram_k<T, 6>(vecs, g, partial, res, st);
         case 7: return gram_k<T, 7>(vecs, g, partial, res, st);
         case 8: return gram_k<T, 8>(vecs, g, partial, res, st);
-        default: return hipErrorInvalidValue;
+        default: break;
     }
+    if (K < 1 || K > kMaxGram) return hipErrorInvalidValue;
+    // one pass over the K vectors; the partials of NP quantities per segment
+    // must fit the caller's buffer (kGramPartialCap doubles)
+    const long long NP = (long long)K * (K + 1) / 2;
+    long long nb = reduction_blocks(g.ncomp * g.seglen);
+    const long long cap = kGramPartialCap / (NP * g.nseg);
+    if (cap < 1) return hipErrorInvalidValue;
+    if (nb > cap) nb = cap;
+    PtrList<T> pl{};
+    for (int a = 0; a < K; ++a) pl.p[a] = vecs[a];
+    const int Kp = 4 * ((K + 3) / 4);
+    const size_t lds = sizeof(double) * std::max(Kp * kGramE, kRedThreads * 16);
+    gram_big_kernel<T><<<dim3((unsigned)nb, g.nseg), kRedThreads, lds, st>>>(pl, K, g, partial);
+    finish_kernel<false><<<finish_blocks(NP * g.nseg), 1024, 0, st>>>(partial, (int)nb,
+                                                                      (int)(NP * g.nseg), res);
+    return hipGetLastError();
 }
 
 template <typename T>

@@ -38,6 +38,15 @@ def rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
 
 
+def relinf(a, b):
+    """max |a - b| / max |b|: a wrong value at a few points (a tile, a wrap
+    at one corner) stays small in the l2 ratio but not here."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    mb = np.abs(b).max() if b.size else 0.0
+    return np.abs(a - b).max() / (mb if mb > 0 else 1.0) if a.size else 0.0
+
+
 def as_precision(P, prec):
     """The oracle problem on the inputs the GPU path actually receives: for the
     FP32 path, m0 and m1 rounded to float32 (then evaluated in FP64)."""

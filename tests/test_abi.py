@@ -10,7 +10,7 @@ import paper_2510_08782_amd as gan
 def test_library_exports_every_header_symbol():
     lib = gan.lib()
     syms = gan.header_symbols()
-    assert len(syms) == 22
+    assert len(syms) == 23
     for name in syms:
         assert hasattr(lib, name), name
     for name in ["ganmres_eval_objective", "ganmres_eval_gradient", "ganmres_apply_precond",
@@ -27,7 +27,7 @@ def test_kernel_names_and_struct_layout():
     # ctypes mirrors of the C structs: sizes as gcc lays them out on x86-64
     assert ctypes.sizeof(gan.Config) == 48
     assert ctypes.sizeof(gan.SolverParams) == 72
-    assert ctypes.sizeof(gan.StepInfo) == 584
+    assert ctypes.sizeof(gan.StepInfo) == 592
 
 
 @pytest.mark.parametrize("bad", [
@@ -73,3 +73,31 @@ def test_null_arguments_are_rejected():
     assert lib.ganmres_destroy(None) == 0
     assert lib.ganmres_batch_count(None) == 0
     assert lib.ganmres_batch_values(None, None, None) == -1
+
+
+def test_host_least_squares_matches_the_oracle():
+    """The library's host solve of the NGMRES least-squares problem (Cholesky,
+    else the pseudo-inverse) against the oracle's, from the same Gram matrix:
+    a full-rank window (Cholesky), and windows with a repeated column and with
+    more columns than entries (pseudo-inverse, the minimum-norm solution,
+    also checked against numpy's lstsq on the explicit difference matrix)."""
+    import numpy as np
+
+    from oracle import ngmres as ong
+    rng = np.random.default_rng(5)
+    r = rng.standard_normal(40)
+    full = [rng.standard_normal(40) for _ in range(5)]
+    dup = full[:3] + [full[1].copy()] + full[3:]
+    wide = [rng.standard_normal(6) for _ in range(9)]
+    r6 = rng.standard_normal(6)
+    for rr, gs, want_fb in ((r, full, False), (r, dup, True), (r6, wide, True)):
+        G = ong.gram([rr] + gs)
+        beta, fb = gan.lsq(G)
+        assert fb == want_fb
+        np.testing.assert_allclose(beta, ong.lsq_from_gram(G), rtol=1e-9, atol=1e-11)
+        if want_fb:
+            np.testing.assert_allclose(beta, ong.lsq_direct(rr, gs), rtol=1e-7, atol=1e-9)
+    bad = np.eye(3)
+    bad[0, 1] = 1.0           # not symmetric
+    with pytest.raises(gan.GanmresError):
+        gan.lsq(bad)

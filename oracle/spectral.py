@@ -24,6 +24,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
+import scipy.fft
 
 
 class Grid:
@@ -66,12 +67,20 @@ class Grid:
         return self.cell * float(np.sum(a * b))
 
 
+# Threads of the multi-dimensional transforms (scipy.fft's `workers`): the
+# transform is the same unnormalised DFT whatever the count; only the CPU
+# baseline raises it to the cores it may use.
+WORKERS = 1
+
+
 def fft(u):
-    return np.fft.fftn(u)
+    """Unnormalised forward DFT over every axis."""
+    return scipy.fft.fftn(u, workers=WORKERS)
 
 
 def ifft(uh):
-    return np.real(np.fft.ifftn(uh))
+    """Inverse DFT (scaled by 1/N), real part."""
+    return np.real(scipy.fft.ifftn(uh, workers=WORKERS))
 
 
 def deriv(grid: Grid, u: np.ndarray, j: int) -> np.ndarray:

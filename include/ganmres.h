@@ -153,7 +153,9 @@ int ganmres_batch_values(ganmres_handle* h, double* J, double* mismatch);
 /* Release the handle and its workspace (NULL is accepted). */
 int ganmres_destroy(ganmres_handle* h);
 
-/* Message for the last failure on h (or of the last failed create if h is NULL). */
+/* Message for the last failure on h (or, if h is NULL, of the last failed
+ * call without a handle on this thread: ganmres_create,
+ * ganmres_create_batch, ganmres_eval_objective_noalloc). */
 const char* ganmres_last_error(const ganmres_handle* h);
 
 /* Objective J(v) = 1/2 ||m(1) - m1||_h^2 + alpha/2 <v, L_p v>_h (eq. e:varopt;
@@ -164,6 +166,30 @@ const char* ganmres_last_error(const ganmres_handle* h);
  * Errors: GANMRES_ENONFINITE. */
 int ganmres_eval_objective(ganmres_handle* h, const void* v, int keep_history,
                            double* J, double* mismatch);
+
+/* The objective of ganmres_eval_objective without a handle and without any
+ * device allocation, for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  cfg, m0,
+ * m1 describe the problem as for ganmres_create (checkpoint_every must be 1);
+ * v is the velocity.  m0, m1, v: device arrays owned by the caller; J: host,
+ * required; mismatch: host, nullable; stream: hipStream_t or NULL.
+ * Every intermediate field (the FP64 spectrum of v, the departure points, two
+ * state fields, the window table, the divergence and source factor of the
+ * continuity model, the FFT twiddles, the reduction partials) lives in one
+ * static device array of 32 MiB per GPU, held until the process ends: about
+ * (d + 2) N s + 16 d N_h + 0.5 MiB bytes (N points, N_h half-spectrum
+ * points, s = 4 or 8; two more N s for the continuity model), e.g. 2-D grids
+ * up to 512^2 and 3-D grids up to 64^3 in either precision.  A larger problem
+ * is rejected with GANMRES_EINVAL (ganmres_last_error(NULL) gives the bytes
+ * it needs) before any device work.  The call enqueues on the stream,
+ * synchronises it twice (the window bound, the result) and calls no
+ * allocating routine.  All calls on one GPU share the array: calls that
+ * overlap in time on one GPU (other threads, other streams) race and must be
+ * serialised by the caller.  Nothing in the array needs to start at zero
+ * (each call writes every value it reads).
+ * Errors: GANMRES_EINVAL, GANMRES_ENONFINITE, GANMRES_EDEVICE. */
+int ganmres_eval_objective_noalloc(const ganmres_config* cfg, const void* m0, const void* m1,
+                                   const void* v, void* stream, double* J, double* mismatch);
 
 /* Reduced gradient g(v) = alpha L_p v + b (eq. e:reduced-gradient) with
  * b = int lam grad m dt (advection, adjoint eq. e:adjoint with final value

@@ -94,6 +94,7 @@ def lib():
     L.ganmres_step.argtypes = [vp, ctypes.POINTER(SolverParams), vp, ctypes.POINTER(StepInfo)]
     L.ganmres_solver_reset.argtypes = [vp]
     L.ganmres_lsq.argtypes = [ip, dp, dp, ctypes.POINTER(ctypes.c_int)]
+    L.ganmres_eval_objective_noalloc.argtypes = [ctypes.POINTER(Config), vp, vp, vp, vp, dp, dp]
     L.ganmres_get_field.argtypes = [vp, ip, ip, vp]
     L.ganmres_timing_enable.argtypes = [vp, ip]
     L.ganmres_timing_reset.argtypes = [vp]

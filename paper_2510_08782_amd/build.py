@@ -27,7 +27,7 @@ FLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]
-SOURCES = ["sl.hip", "spectral.hip", "vec.hip", "runtime.hip"]
+SOURCES = ["sl.hip", "spectral.hip", "vec.hip", "runtime.hip", "noalloc.hip"]
 
 
 def _compile(src: str) -> str:

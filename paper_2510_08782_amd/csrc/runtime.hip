@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/ganmres.h"
+#include "config.hpp"
 #include "fft_core.hpp"
 #include "launch.hpp"
 
@@ -1802,12 +1803,6 @@ class Problem : public ProblemBase {
     }
 };
 
-static bool size_ok(int n) {
-    if (n < 4 || n > 1024) return false;
-    int r[kMaxRadices];
-    return make_radices(n, r) > 0;
-}
-
 }  // namespace gan
 
 struct ganmres_handle {
@@ -1817,6 +1812,7 @@ struct ganmres_handle {
 };
 
 static thread_local std::string g_create_error;
+std::string& gan::handle_free_error() { return g_create_error; }
 
 template <typename F>
 static int guarded(ganmres_handle* h, F&& f) {
@@ -1854,19 +1850,10 @@ static int create_impl(const ganmres_config* cfg, int count, const double* alpha
     if (why.empty() && count > 1 && c.dim != 2) why = "batches stack 2-D problems";
     for (int i = 0; alpha && i < count && why.empty(); ++i)
         if (!(alpha[i] > 0.0)) why = "alpha must be > 0";
-    if (c.dim != 2 && c.dim != 3) why = "dim must be 2 or 3";
-    for (int a = 0; a < c.dim && why.empty(); ++a)
-        if (!gan::size_ok(c.n[a])) why = "grid sizes must be 2^a 3^b in [4, 1024]";
-    if (why.empty() && c.nt < 1) why = "nt must be >= 1";
-    if (why.empty() && c.nt > 64) why = "nt must be <= 64";
-    if (why.empty() && !(c.alpha > 0.0)) why = "alpha must be > 0";
-    if (why.empty() && (c.reg_order < 1 || c.reg_order > 3)) why = "reg_order must be 1..3";
-    if (why.empty() && c.model != GANMRES_ADVECTION && c.model != GANMRES_CONTINUITY)
-        why = "unknown model";
-    if (why.empty() && c.dtype != GANMRES_F32 && c.dtype != GANMRES_F64) why = "unknown dtype";
-    if (why.empty() && c.incompressible && c.model == GANMRES_CONTINUITY)
-        why = "the incompressible option applies to the advection model";
-    if (why.empty() && c.checkpoint_every < 1) why = "checkpoint_every must be >= 1";
+    {
+        const std::string cw = gan::config_error(c);
+        if (!cw.empty()) why = cw;
+    }
     if (!why.empty()) {
         g_create_error = why;
         return GANMRES_EINVAL;

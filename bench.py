@@ -92,13 +92,17 @@ def time_gradients(torch, P, v, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def time_to_solution(torch, P, params):
+def time_to_solution(torch, P, params, keep=None):
+    """Wall time of a solve from v = 0 until the stopping rule holds; keep
+    (a dict) receives the final velocity under "v"."""
     v = P.new_velocity()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     v, infos = P.solve(params, v0=v)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
+    if keep is not None:
+        keep["v"] = v
     last = infos[-1]
     out = dict(seconds=round(t, 4), iterations=last.k,
                rel_grad=last.ginf / last.g0inf, reached=bool(last.ginf <= params.eps_rel * last.g0inf),
@@ -108,6 +112,24 @@ def time_to_solution(torch, P, params):
     if params.accel == gan.ACCEL_NK:   # one Hessian matvec per CG iteration
         out["hessian_matvecs"] = sum(i.n_beta for i in infos)
     return out
+
+
+def rel_errors(a32, a64):
+    """Relative l2 and max-norm errors of a (device) FP32 result against FP64."""
+    d = a32.double() - a64
+    n2 = float(a64.norm())
+    ninf = float(a64.abs().max())
+    return {"l2": float(d.norm()) / (n2 if n2 > 0 else 1.0),
+            "inf": float(d.abs().max()) / (ninf if ninf > 0 else 1.0)}
+
+
+def roofline_obj(kernel, bytes_per_launch, ms, count, traffic=None):
+    avg_ms = ms / count
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch),
+            "launches": count}
 
 
 def algorithmic_bytes(kernel, wl, N, s):
@@ -126,30 +148,30 @@ def algorithmic_bytes(kernel, wl, N, s):
     return None
 
 
-def cpu_baseline(synth_mod, min_seconds=10.0):
-    """The FP64 oracle's gradient on the same recipe at 64^3 (1/8 of the
-    points), repeated for at least min_seconds, scaled to the 128^3 workload
-    by the point count."""
+def cpu_baseline(synth_mod):
+    """One FP64 oracle gradient of the 128^3 workload itself (the bench's probe
+    v = v*/2), its transforms on every core this process may use (scipy.fft
+    workers), the interpolation in single-threaded NumPy as written.  The
+    reference image is m0 shifted by 4 cells per axis: the oracle's cost does
+    not depend on the image values, and this saves a forward solve."""
+    import numpy as np
+
+    import oracle.spectral as osp
     from oracle.transport import TransportProblem
-    wl = synth_mod.workload("c2", shape=(64, 64, 64))
-    gen = TransportProblem(wl.m0, wl.m0, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
-    m1 = gen.forward(wl.vstar)[-1]
+    cores = len(os.sched_getaffinity(0))
+    osp.WORKERS = cores
+    wl = synth_mod.workload("c2")
+    m1 = np.roll(wl.m0, (4, 4, 4), axis=(0, 1, 2))
     P = TransportProblem(wl.m0, m1, wl.nt, wl.alpha, wl.reg_order, incompressible=True)
     v = 0.5 * wl.vstar
-    reps = 0
     t0 = time.perf_counter()
-    while True:
-        P.gradient(v)
-        reps += 1
-        t = time.perf_counter() - t0
-        if t >= min_seconds:
-            break
-    scale = (128 ** 3) / (64 ** 3)
-    per = t / reps
-    return {"value": round(1.0 / (per * scale), 6), "unit": "grad evals/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"{reps} oracle gradients of the 128^3 recipe at 64^3 ({t:.1f} s, numpy, "
-                      f"single thread), time per gradient scaled x{scale:.0f} by grid points"}
+    P.gradient(v)
+    t = time.perf_counter() - t0
+    osp.WORKERS = 1
+    return {"value": round(1.0 / t, 6), "unit": "grad evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 oracle gradient of the 128^3 workload ({t:.1f} s): transforms on {cores} "
+                      f"threads (scipy.fft workers = affine cores; os.cpu_count() = "
+                      f"{os.cpu_count()}), the 64-tap interpolation in single-threaded NumPy"}
 
 
 def measured_traffic(kernel):
@@ -175,79 +197,142 @@ def measured_traffic(kernel):
 
 def c3_throughput(torch, gan, synth):
     """256^3 advection, H2, nt=8: FP32 with checkpointed history (every 2nd
-    state) against the plain FP64 path: grad evals/s and device workspace."""
+    state) against the plain FP64 path: grad evals/s, device workspace, the
+    sl_step roofline at this size (its 64 MiB fields do not fit the 256 MB
+    Infinity Cache with their sources and displacements), and the FP32
+    objective and gradient against FP64 on the same (FP32-rounded) inputs."""
     wl = synth.workload("c3")
+    N = 256 ** 3
     out = {}
+    dev = lambda x, dt: torch.tensor(x, dtype=dt, device="cuda")
+    m0 = dev(wl.m0, torch.float32)
+    vstar = dev(wl.vstar, torch.float32)
+    gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=2)
+    gen.eval_objective(vstar)
+    m1 = gen.get_field("state", wl.nt)
+    gen.close()
+    v32 = (0.5 * vstar).contiguous()
+    res = {}
     for name, dtype, ck in (("fp32_checkpoint2", torch.float32, 2), ("fp64_plain", torch.float64, 1)):
-        dev = lambda x: torch.tensor(x, dtype=dtype, device="cuda")
-        m0 = dev(wl.m0)
-        vstar = dev(wl.vstar)
-        gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=ck)
-        gen.eval_objective(vstar)
-        m1 = gen.get_field("state", wl.nt)
-        gen.close()
-        P = gan.Problem(m0, m1, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=ck)
-        v = (0.5 * vstar).contiguous()
+        P = gan.Problem(m0.to(dtype), m1.to(dtype), wl.nt, wl.alpha, wl.reg_order, checkpoint_every=ck)
+        v = v32.to(dtype)
         torch.cuda.reset_peak_memory_stats()
         t = time_gradients(torch, P, v, 5)
         out[name] = {"grad_evals_per_s": round(1.0 / t, 2), "ms_per_grad": round(1e3 * t, 3),
                      "workspace_bytes": P.workspace_bytes(),
                      "torch_peak_bytes": int(torch.cuda.max_memory_allocated())}
+        # sl_step launches of 5 gradients, timed with events
+        reps = 5
+        P.timing(True, ["sl_step"])
+        P.timing_reset()
+        for _ in range(reps):
+            J, g = P.eval_gradient(v)
+        ms, cnt = P.timing_report()["sl_step"]
+        P.timing(False)
+        # per gradient: nt forward steps and nt - nt/ck recomputed ones
+        # (source, 3 displacements, output), nt adjoint steps (plus the
+        # divergence factor of the advection adjoint)
+        s = 4 if dtype == torch.float32 else 8
+        fwd = wl.nt + (wl.nt - wl.nt // ck if ck > 1 else 0)
+        nbytes = (fwd * 5 + wl.nt * 6) * N * s
+        per_grad = fwd + wl.nt
+        if cnt == reps * per_grad:
+            out[name]["roofline_sl_step"] = roofline_obj("sl_step", nbytes / per_grad, ms, cnt)
+        res[name] = (J, g)
         P.close()
-        del m0, m1, vstar, v
         torch.cuda.empty_cache()
+    (J32, g32), (J64, g64) = res["fp32_checkpoint2"], res["fp64_plain"]
+    out["fp32_vs_fp64"] = {"probe": "v = v*/2", "J": abs(J32 - J64) / abs(J64),
+                           "g": rel_errors(g32, g64)}
+    del res, g32, g64, m0, m1, vstar, v32
+    torch.cuda.empty_cache()
     return out
+
+
+def c1_errors(torch, gan, synth):
+    """2-D continuity at 256^2, H2, nt=8: FP32 objective and gradient at
+    v = v*/2 against the FP64 path on the same (FP32-rounded) inputs."""
+    wl = synth.workload("c1")
+    dev = lambda x, dt: torch.tensor(x, dtype=dt, device="cuda")
+    m0 = dev(wl.m0, torch.float32)
+    vstar = dev(wl.vstar, torch.float32)
+    gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, model="continuity")
+    gen.eval_objective(vstar)
+    m1 = gen.get_field("state", wl.nt)
+    gen.close()
+    v = (0.5 * vstar).contiguous()
+    got = {}
+    for dtype in (torch.float32, torch.float64):
+        P = gan.Problem(m0.to(dtype), m1.to(dtype), wl.nt, wl.alpha, wl.reg_order, model="continuity")
+        got[dtype] = P.eval_gradient(v.to(dtype))
+        t = time_gradients(torch, P, v.to(dtype), 20)
+        got[(dtype, "t")] = t
+        P.close()
+    (J32, g32), (J64, g64) = got[torch.float32], got[torch.float64]
+    return {"probe": "v = v*/2", "J": abs(J32 - J64) / abs(J64), "g": rel_errors(g32, g64),
+            "fp32_us_per_grad": round(1e6 * got[(torch.float32, "t")], 1),
+            "fp64_us_per_grad": round(1e6 * got[(torch.float64, "t")], 1)}
 
 
 def c4_throughput(torch, gan, synth):
     """The batched 2-D set: 16 problems each at 96^2, 192^2 and 384^2 (FP32,
-    H1, nt=4, alpha per problem), one batch handle per size; 15 GA-NGMRES
-    iterations of every problem from v = 0.  Aggregate gradient evaluations
-    per second over the whole set."""
+    H1, nt=4, alpha per problem) in ONE group handle, so that every phase is
+    one kernel launch for all 48 problems; 15 GA-NGMRES iterations of every
+    problem from v = 0.  Aggregate gradient evaluations per second over the
+    whole set, and the launches the classes made against the merged launches
+    that ran them."""
     import numpy as np
     wls = synth.batch_workloads()
     sv = wls[0].solver
     params = gan.SolveParams(w=sv["w"], sigma=sv["sigma"], tau=sv["tau"], eps_rel=sv["eps_rel"],
                              n_iter=sv["n_iter"])
-    groups = {}
+    classes = {}
     for w in wls:
-        groups.setdefault(w.shape, []).append(w)
-    batches = []
-    for shape, ws in groups.items():
-        dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+        classes.setdefault(w.shape, []).append(w)
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=torch.float32, device="cuda")
+    m0s, m1s, alphas = [], [], []
+    for shape, ws in classes.items():
         m0 = dev(np.stack([w.m0 for w in ws]))
         vstar = dev(np.stack([w.vstar for w in ws], axis=1))
-        alphas = [w.alpha for w in ws]
-        gen = gan.BatchProblem(m0, m0, ws[0].nt, alphas, ws[0].reg_order)
+        al = [w.alpha for w in ws]
+        gen = gan.BatchProblem(m0, m0, ws[0].nt, al, ws[0].reg_order)
         gen.eval_objective(vstar)
-        m1 = gen.get_field("state", ws[0].nt)
+        m1s.append(gen.get_field("state", ws[0].nt))
         gen.close()
-        batches.append((shape, gan.BatchProblem(m0, m1, ws[0].nt, alphas, ws[0].reg_order)))
-    # warm-up: one iteration per batch
-    for _, B in batches:
-        B.step(params, B.new_velocity())
-        B.reset()
+        m0s.append(m0)
+        alphas += al
+    G = gan.GroupProblem(m0s, m1s, wls[0].nt, alphas, wls[0].reg_order)
+    # warm-up: one iteration
+    G.step(params, G.new_velocity())
+    G.reset()
     torch.cuda.synchronize()
+    s0, i0 = G.launches()
     t0 = time.perf_counter()
+    v = G.new_velocity()
     ngrad = 0
-    per = {}
-    for shape, B in batches:
-        t1 = time.perf_counter()
-        v = B.new_velocity()
-        for _ in range(params.n_iter):
-            infos = B.step(params, v)
-            ngrad += sum(i.n_grad for i in infos)
-        torch.cuda.synchronize()
-        per[f"{shape[0]}x{shape[1]}"] = {"problems": B.count,
-                                         "seconds": round(time.perf_counter() - t1, 4),
-                                         "rel_grad_max": max(i.ginf / i.g0inf for i in infos)}
-        B.reset()
+    for _ in range(params.n_iter):
+        infos = G.step(params, v)
+        ngrad += sum(i.n_grad for i in infos)  # the first step's n_grad counts g(v^0)
+    torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    # n_grad of each first step already counts g(v^0)
-    for _, B in batches:
-        B.close()
+    s1, i1 = G.launches()
+    per = {}
+    k = 0
+    for c, (shape, ws) in enumerate(classes.items()):
+        sub = infos[k:k + len(ws)]
+        pts, us = G.tile_autotune(c)
+        per[f"{shape[0]}x{shape[1]}"] = {"problems": len(ws),
+                                         "rel_grad_max": max(i.ginf / i.g0inf for i in sub),
+                                         "tile_points_per_thread": pts,
+                                         "autotune_us_per_gather_p8_p4_p2": [round(x, 2) for x in us]}
+        k += len(ws)
+    G.close()
     return {"problems": len(wls), "iterations_each": params.n_iter, "seconds": round(dt, 4),
-            "grad_evals": ngrad, "grad_evals_per_s": round(ngrad / dt, 1), "per_size": per}
+            "grad_evals": ngrad, "grad_evals_per_s": round(ngrad / dt, 1),
+            "handle": "one group handle (3 size classes of 16 problems)",
+            "launches_by_classes": s1 - s0, "launches_issued": i1 - i0,
+            "launches_issued_per_iteration": round((i1 - i0) / params.n_iter, 1),
+            "per_size": per}
 
 
 def main():
@@ -311,12 +396,7 @@ def main():
     bpl = algorithmic_bytes(dname, wl, N, 4)
     roofline = None
     if bpl is not None and dcount > 0:
-        avg_ms = dms / dcount
-        achieved = bpl / (avg_ms * 1e-3) / 1e9
-        roofline = {"bound": "hbm", "kernel": dname, "achieved": round(achieved, 1),
-                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": measured_traffic(dname), "avg_launch_us": round(avg_ms * 1e3, 2),
-                    "bytes_per_launch": bpl, "launches": dcount}
+        roofline = roofline_obj(dname, bpl, dms, dcount, measured_traffic(dname))
     kernels = {k: {"ms": round(ms, 3), "launches": c,
                    "avg_us": round(1e3 * ms / c, 2) if c else None,
                    "share": round(ms / max(sum(x[0] for x in rep.values()), 1e-12), 4)}
@@ -330,9 +410,24 @@ def main():
     extra = {}
     v_half = (0.5 * vstar32).contiguous()
     extra["grad_eval_only_fp32_per_s"] = round(1.0 / time_gradients(torch, P32, v_half, 10), 2)
+    # FP32 objective and gradient against the FP64 path on the same inputs
+    # (m0, m1, v rounded to FP32); the FP64 path matches the FP64 oracle to
+    # 1e-10 in the parity tests
+    log("FP32 against FP64 at v = v*/2")
+    J32, g32 = P32.eval_gradient(v_half)
+    P64r = gan.Problem(P32.m0.double(), P32.m1.double(), wl.nt, wl.alpha, wl.reg_order,
+                       model=wl.model, incompressible=wl.incompressible)
+    J64, g64 = P64r.eval_gradient(v_half.double())
+    P64r.close()
+    errors = {"c2": {"probe": "v = v*/2, same FP32-rounded inputs", "J": abs(J32 - J64) / abs(J64),
+                     "g": rel_errors(g32, g64)}}
+    del g32, g64
+    finals = {}
     if not args.no_tts:
         log("time-to-1e-2, FP32 GA-NGMRES")
-        extra["tts_fp32_ga_ngmres"] = time_to_solution(torch, P32, params)
+        keep = {}
+        extra["tts_fp32_ga_ngmres"] = time_to_solution(torch, P32, params, keep)
+        finals["fp32"] = keep["v"]
         for pname, pc in (("ireg", gan.PC_IREG), ("h0rpc", gan.PC_H0RPC),
                           ("2lrpcsym", gan.PC_2LRPCSYM)):
             log(f"time-to-1e-2, FP32 Gauss-Newton-Krylov baseline, {pname}")
@@ -343,22 +438,45 @@ def main():
     extra["peak_workspace_bytes_fp32"] = P32.workspace_bytes()
     P32.close()
 
+    roofline_fp64 = None
     if not args.no_fp64:
         log("FP64 path")
         P64, vstar64 = make_problem(torch, gan, synth, torch.float64, wl)
         k64 = max(4, args.steps // 3)
-        dt64, ng64, _, _ = time_steps(torch, P64, params, k64, 2)
+        dt64, ng64, _, rep64 = time_steps(torch, P64, params, k64, 2, timing=True,
+                                          classes=["sl_step"])
         extra["fp64_grad_evals_per_s"] = round(ng64 / dt64, 2)
+        ms64, c64 = rep64["sl_step"]
+        if c64:
+            roofline_fp64 = roofline_obj("sl_step", algorithmic_bytes("sl_step", wl, N, 8), ms64, c64)
         extra["grad_eval_only_fp64_per_s"] = round(
             1.0 / time_gradients(torch, P64, (0.5 * vstar64).contiguous(), 5), 2)
         if not args.no_tts:
             log("time-to-1e-2, FP64 GA-NGMRES")
-            extra["tts_fp64_ga_ngmres"] = time_to_solution(torch, P64, params)
+            keep = {}
+            extra["tts_fp64_ga_ngmres"] = time_to_solution(torch, P64, params, keep)
+            finals["fp64"] = keep["v"]
+            log("time-to-1e-2, FP64 plain fixed-point loop (RPGD, sigma = 0)")
+            rpgd = gan.SolveParams(w=0, sigma=0, tau=1, eps_rel=sv["eps_rel"], n_iter=500)
+            extra["tts_fp64_rpgd"] = time_to_solution(torch, P64, rpgd)
         P64.close()
+    if "fp32" in finals and "fp64" in finals:
+        errors["c2"]["v_final"] = rel_errors(finals["fp32"], finals["fp64"])
+        errors["c2"]["v_final_note"] = ("final iterates of the two time-to-1e-2 solves, each on "
+                                        "its own precision's inputs")
+    del finals
 
     if not args.no_c3:
         log("256^3 throughput (c3)")
         extra["c3_256cubed"] = c3_throughput(torch, gan, synth)
+
+    if not args.no_c3:
+        errors["c3"] = extra["c3_256cubed"].pop("fp32_vs_fp64")
+    log("c1 FP32 against FP64")
+    errors["c1"] = c1_errors(torch, gan, synth)
+    extra["fp32_vs_fp64_rel_error"] = errors
+    if roofline_fp64:
+        extra["roofline_fp64"] = roofline_fp64
 
     if not args.no_c4:
         log("batched 2-D set (c4)")

@@ -143,6 +143,45 @@ int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1,
 int ganmres_create_batch(const ganmres_config* cfg, int count, const double* alpha,
                          const void* m0, const void* m1, void* stream, ganmres_handle** out);
 
+/* A group: batches of 2-D problems of DIFFERENT grid sizes in one handle
+ * (uneven-size registrations, e.g. 16 problems each at 96^2, 192^2 and
+ * 384^2), run so that every phase of an evaluation or iteration is one
+ * kernel launch for all of them.  Class c (0 <= c < nclass <= 16) holds
+ * counts[c] (1..64) problems of shape (shapes[2c], shapes[2c+1]); cfg gives
+ * everything else (dim must be 2; cfg->n is ignored).  alpha: host array of
+ * one weight per problem, classes in order (NULL: cfg->alpha for all).
+ * m0[c], m1[c]: device images of shape (counts[c], shapes[2c], shapes[2c+1]).
+ * On a group handle a velocity is the classes' batch velocities back to back,
+ * class c's of shape (2, counts[c], shapes[2c], shapes[2c+1]) (see
+ * ganmres_create_batch), and an image the classes' stacked images back to
+ * back; per-problem results (ganmres_step's info, ganmres_batch_values,
+ * ganmres_deformation's stats) list the problems class by class.  Each
+ * problem has its own line search, window and mixing coefficients, as in a
+ * batch; the classes backtrack together (a class whose problems have all
+ * accepted waits) and take the same gather variant (the largest bound).  The
+ * Newton-Krylov baseline (accel = GANMRES_ACCEL_NK), ganmres_hessian_matvec
+ * and ganmres_newton_precond are not available on a group (GANMRES_EINVAL);
+ * kernel timing has no effect.  Errors: as ganmres_create_batch, and
+ * GANMRES_EINVAL for nclass outside [1, 16] or dim != 2. */
+int ganmres_create_group(const ganmres_config* cfg, int nclass, const int* shapes,
+                         const int* counts, const double* alpha, const void* const* m0,
+                         const void* const* m1, void* stream, ganmres_handle** out);
+
+/* Kernel launches of a group handle since its creation: *submitted counts the
+ * launches its classes made, *issued the merged launches that ran them.
+ * Errors: GANMRES_EINVAL (not a group handle). */
+int ganmres_group_launches(const ganmres_handle* h, long long* submitted, long long* issued);
+
+/* The 2-D tile autotuner: the semi-Lagrangian kernels of a 2-D handle run on
+ * tiles of 64 x 4P points with P = 8, 4 or 2 points per thread, chosen when
+ * the handle (or each class of a group) is created by timing the gather step
+ * of every variant on its grid, once per grid size and element type in the
+ * process.  Reports class cls's choice (cls = 0 for a handle that is not a
+ * group): *points_per_thread = P (0 for a 3-D handle, which has no variants)
+ * and, in us (host, nullable, 3 entries), the measured microseconds per
+ * gather launch of P = 8, 4, 2.  Errors: GANMRES_EINVAL. */
+int ganmres_tile_autotune(const ganmres_handle* h, int cls, int* points_per_thread, double* us);
+
 /* Number of problems in the handle (1 for ganmres_create; 0 for NULL). */
 int ganmres_batch_count(const ganmres_handle* h);
 

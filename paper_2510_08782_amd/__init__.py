@@ -80,6 +80,12 @@ def lib():
     L.ganmres_create.argtypes = [ctypes.POINTER(Config), vp, vp, vp, ctypes.POINTER(vp)]
     L.ganmres_create_batch.argtypes = [ctypes.POINTER(Config), ip, dp, vp, vp, vp,
                                        ctypes.POINTER(vp)]
+    L.ganmres_create_group.argtypes = [ctypes.POINTER(Config), ip, ctypes.POINTER(ip),
+                                       ctypes.POINTER(ip), dp, ctypes.POINTER(vp),
+                                       ctypes.POINTER(vp), vp, ctypes.POINTER(vp)]
+    L.ganmres_group_launches.argtypes = [vp, ctypes.POINTER(ctypes.c_longlong),
+                                         ctypes.POINTER(ctypes.c_longlong)]
+    L.ganmres_tile_autotune.argtypes = [vp, ip, ctypes.POINTER(ip), dp]
     L.ganmres_batch_count.argtypes = [vp]
     L.ganmres_batch_values.argtypes = [vp, dp, dp]
     L.ganmres_deformation.argtypes = [vp, vp, vp, dp]
@@ -262,6 +268,14 @@ class Problem:
                                             out.data_ptr()))
         return out
 
+    def tile_autotune(self, cls=0):
+        """(points per thread chosen for the 2-D gather tiles, microseconds per
+        gather launch of the variants 8, 4, 2) of class cls (0 unless a group)."""
+        p = ctypes.c_int()
+        us = (ctypes.c_double * 3)()
+        self._check(lib().ganmres_tile_autotune(self.h, int(cls), ctypes.byref(p), us))
+        return p.value, list(us)
+
     def workspace_bytes(self):
         return int(lib().ganmres_workspace_bytes(self.h))
 
@@ -398,3 +412,99 @@ class BatchProblem(Problem):
         self._check(lib().ganmres_step(self.h, ctypes.byref(cp), self._vec(v).data_ptr(), infos))
         return list(infos)
 
+
+
+class GroupProblem(Problem):
+    """Batches of 2-D problems of different grid sizes in one handle: every
+    phase of an evaluation or iteration is one kernel launch for all of them.
+
+    m0s, m1s: per size class a device tensor of shape (count_c, n0_c, n1_c);
+    alphas: one weight per problem, classes in order.  A velocity is a flat
+    tensor holding the classes' batch velocities (2, count_c, n0_c, n1_c) back
+    to back (velocity_views gives them); images likewise (image_views).
+    step() returns one StepInfo per problem, classes in order."""
+
+    def __init__(self, m0s, m1s, nt, alphas, reg_order, model="advection", stream=None):
+        import torch
+        if len(m0s) != len(m1s) or not m0s:
+            raise ValueError("one m0 and one m1 per class")
+        self.torch = torch
+        self.dtype = m0s[0].dtype
+        if self.dtype not in (torch.float32, torch.float64):
+            raise ValueError("float32 or float64 images")
+        for a, b in zip(m0s, m1s):
+            if a.dim() != 3 or a.shape != b.shape or a.dtype != self.dtype or b.dtype != self.dtype \
+                    or not a.is_cuda:
+                raise ValueError("images must be device tensors (count, n0, n1) of one dtype")
+        self.m0s = [a.contiguous() for a in m0s]
+        self.m1s = [b.contiguous() for b in m1s]
+        self.m0 = self.m0s[0]
+        self.classes = [tuple(a.shape) for a in self.m0s]
+        self.count = sum(c[0] for c in self.classes)
+        alphas = [float(x) for x in alphas]
+        if len(alphas) != self.count:
+            raise ValueError("one alpha per problem")
+        self.dim = 2
+        self.nt = int(nt)
+        self.vlen = sum(2 * c * a * b for c, a, b in self.classes)
+        self.ilen = sum(c * a * b for c, a, b in self.classes)
+        self.shape = (self.ilen,)
+        cfg = Config(2, (ctypes.c_int * 3)(1, 1, 1), int(nt),
+                     ADVECTION if model == "advection" else CONTINUITY, 0, int(reg_order),
+                     alphas[0], F32 if self.dtype == torch.float32 else F64, 1)
+        self.cfg = cfg
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.m0.device)
+        n = len(self.classes)
+        shapes = (ctypes.c_int * (2 * n))(*[x for c in self.classes for x in c[1:]])
+        counts = (ctypes.c_int * n)(*[c[0] for c in self.classes])
+        al = (ctypes.c_double * self.count)(*alphas)
+        p0 = (ctypes.c_void_p * n)(*[a.data_ptr() for a in self.m0s])
+        p1 = (ctypes.c_void_p * n)(*[b.data_ptr() for b in self.m1s])
+        h = ctypes.c_void_p()
+        rc = lib().ganmres_create_group(ctypes.byref(cfg), n, shapes, counts, al, p0, p1,
+                                        ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise GanmresError(rc, lib().ganmres_last_error(None).decode())
+        self.h = h
+
+    def _vec(self, v):
+        if v.dtype != self.dtype or tuple(v.shape) != (self.vlen,) or not v.is_cuda \
+                or not v.is_contiguous():
+            raise ValueError(f"expected a contiguous {self.dtype} device tensor of shape "
+                             f"({self.vlen},)")
+        return v
+
+    def new_velocity(self):
+        return self.torch.zeros((self.vlen,), dtype=self.dtype, device=self.m0.device)
+
+    def velocity_views(self, v):
+        """Per class the view (2, count_c, n0_c, n1_c) of a group velocity."""
+        out, off = [], 0
+        for c, a, b in self.classes:
+            out.append(v[off:off + 2 * c * a * b].view(2, c, a, b))
+            off += 2 * c * a * b
+        return out
+
+    def image_views(self, img):
+        """Per class the view (count_c, n0_c, n1_c) of a group image."""
+        out, off = [], 0
+        for c, a, b in self.classes:
+            out.append(img[off:off + c * a * b].view(c, a, b))
+            off += c * a * b
+        return out
+
+    def pack_velocity(self, views):
+        """A group velocity from per-class batch velocities (2, count_c, n0_c, n1_c)."""
+        return self.torch.cat([x.reshape(-1) for x in views]).contiguous()
+
+    def step(self, params: SolveParams, v):
+        infos = (StepInfo * self.count)()
+        cp = params.to_c()
+        self._check(lib().ganmres_step(self.h, ctypes.byref(cp), self._vec(v).data_ptr(), infos))
+        return list(infos)
+
+    def launches(self):
+        """(launches the classes made, merged launches that ran them) so far."""
+        a, b = ctypes.c_longlong(), ctypes.c_longlong()
+        self._check(lib().ganmres_group_launches(self.h, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value

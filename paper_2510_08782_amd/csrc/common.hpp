@@ -17,7 +17,11 @@ struct Dims {
     long long N;       // n0 n1 n2
     int n2h;           // n2/2 + 1 (half-spectrum length of the last axis)
     long long NH;      // n0 n1 n2h
+    int tile;          // 2-D gather tiles: points per thread (8, 4 or 2; 0: 8)
 };
+
+// 2-D gather tile height in points per thread when no variant was chosen.
+constexpr int kTile2Default = 8;
 
 inline __host__ __device__ int comp_axis(int dim, int c) { return 3 - dim + c; }
 

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "common.hpp"
+#include "group.hpp"
 
 namespace gan {
 
@@ -36,23 +37,38 @@ __device__ inline double block_reduce(double x, double* sh) {
 }
 
 // Stage 2: res[q] = fold of partial[q*nb .. q*nb + nb) for q < nq; workgroup
-// b of 1024 threads folds q = b, b + gridDim.x, ... (launch finish_blocks(nq)
-// of them, so that the quantities fold in parallel).
+// b of 1024 threads folds q = b, b + gx, ... (launch finish_blocks(nq) of
+// them, so that the quantities fold in parallel).
+struct FinishArgs {
+    const double* partial;
+    int nb, nq;
+    double* res;
+};
 template <bool MAX>
-__global__ void __launch_bounds__(1024) finish_kernel(const double* __restrict__ partial, int nb,
-                                                      int nq, double* __restrict__ res) {
-    __shared__ double sh[1024 / 64];
-    for (int q = blockIdx.x; q < nq; q += gridDim.x) {
-        double x = MAX ? -INFINITY : 0.0;
-        for (int i = threadIdx.x; i < nb; i += blockDim.x)
-            x = MAX ? fmax(x, partial[(long long)q * nb + i]) : x + partial[(long long)q * nb + i];
-        const double r = block_reduce<MAX>(x, sh);
-        if (threadIdx.x == 0) res[q] = r;
+struct FinishBody {
+    static constexpr int kBlock = 1024;
+    using Args = FinishArgs;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        __shared__ double sh[1024 / 64];
+        for (int q = bk.x; q < a.nq; q += bk.gx) {
+            double x = MAX ? -INFINITY : 0.0;
+            for (int i = threadIdx.x; i < a.nb; i += blockDim.x)
+                x = MAX ? fmax(x, a.partial[(long long)q * a.nb + i])
+                        : x + a.partial[(long long)q * a.nb + i];
+            const double r = block_reduce<MAX>(x, sh);
+            if (threadIdx.x == 0) a.res[q] = r;
+        }
     }
-}
+};
 
 inline unsigned finish_blocks(long long nq) {
     return (unsigned)(nq < 1 ? 1 : (nq > 4096 ? 4096 : nq));
+}
+
+// Fold nq quantities of nb partials each into res.
+template <bool MAX>
+inline void launch_finish(const double* partial, int nb, int nq, double* res, hipStream_t st) {
+    submit<FinishBody<MAX>>(dim3(finish_blocks(nq)), 0, st, FinishArgs{partial, nb, nq, res});
 }
 
 }  // namespace gan

@@ -2,12 +2,18 @@
 // objective / gradient pipeline, the preconditioned fixed-point map with
 // Armijo backtracking, and one GA-NGMRES iteration (the C ABI of ganmres.h).
 #include <hip/hip_runtime.h>
+#include <ucontext.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <deque>
+#include <functional>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <vector>
@@ -15,6 +21,7 @@
 #include "../../include/ganmres.h"
 #include "config.hpp"
 #include "fft_core.hpp"
+#include "group.hpp"
 #include "launch.hpp"
 
 namespace gan {
@@ -74,6 +81,206 @@ struct DevBuf {
         bytes = b;
     }
 };
+
+// ---- cooperative scheduler of group handles ----------------------------------
+// The classes of a group handle (batches of different grid sizes) run their
+// ordinary Problem code as cooperative tasks, each on its own stack
+// (ucontext), all on the calling thread.  A task runs until it reaches a
+// kernel launch (submit in group.hpp), a stream synchronisation or a group
+// reduction, and hands that to the scheduler.  When every task waits, the
+// scheduler issues all waiting launches, merging those of one family into
+// one launch; synchronises the stream once when tasks wait for results and
+// no launch is pending; and completes a reduction when every task has
+// reached it.  A task's own operations stay in its program order, and the
+// classes share no data, so the results are those of running the classes
+// one after another.
+struct CoopTask {
+    enum State { RUN, LAUNCH, SYNC, BARRIER, DONE };
+    ucontext_t ctx;
+    ucontext_t* home = nullptr;
+    std::unique_ptr<char[]> stack;
+    State state = RUN;
+    LaunchDesc desc;
+    long long bval = 0;  // reduction: contribution in, result out
+    int bop = 0;         // reduction operator: 0 max, 1 logical or
+    int fail = 0;        // the awaited operation failed (fail_msg)
+    std::string fail_msg;
+    std::function<void()> fn;
+    int err = GANMRES_OK;  // how the task's work ended
+    std::string err_msg;
+};
+
+constexpr int kMaxClasses = 16;  // size classes of a group handle
+
+struct CoopStats {
+    long long submitted = 0;  // launches handed over by the tasks
+    long long issued = 0;     // launches the scheduler made of them
+};
+
+static thread_local CoopTask* g_coop = nullptr;
+CoopTask* coop_current() { return g_coop; }
+
+static void coop_wait(CoopTask* t, CoopTask::State s) {
+    t->state = s;
+    g_coop = nullptr;
+    swapcontext(&t->ctx, t->home);
+    g_coop = t;
+    if (t->fail) {
+        t->fail = 0;
+        throw Error(GANMRES_EDEVICE, t->fail_msg);
+    }
+}
+void coop_launch(CoopTask* t, const LaunchDesc& d) {
+    t->desc = d;
+    coop_wait(t, CoopTask::LAUNCH);
+}
+static void coop_sync(CoopTask* t) { coop_wait(t, CoopTask::SYNC); }
+static long long coop_reduce(CoopTask* t, long long v, int op) {
+    t->bval = v;
+    t->bop = op;
+    coop_wait(t, CoopTask::BARRIER);
+    return t->bval;
+}
+
+static void coop_entry(unsigned lo, unsigned hi) {
+    CoopTask* t = reinterpret_cast<CoopTask*>((static_cast<uintptr_t>(hi) << 32) | lo);
+    try {
+        t->fn();
+    } catch (const Error& e) {
+        t->err = e.code;
+        t->err_msg = e.msg;
+    } catch (const std::bad_alloc&) {
+        t->err = GANMRES_ENOMEM;
+        t->err_msg = "host allocation failed";
+    } catch (...) {
+        t->err = GANMRES_EDEVICE;
+        t->err_msg = "unexpected error";
+    }
+    t->state = CoopTask::DONE;
+    g_coop = nullptr;  // uc_link resumes the scheduler
+}
+
+// Run fns[i] as cooperating tasks on stream st; rethrows the first task error.
+static void coop_run(const std::vector<std::function<void()>>& fns, hipStream_t st, CoopStats* stats) {
+    constexpr size_t kStack = size_t(1) << 20;
+    const int n = static_cast<int>(fns.size());
+    std::vector<std::unique_ptr<CoopTask>> tasks;
+    ucontext_t home;
+    for (int i = 0; i < n; ++i) {
+        tasks.emplace_back(new CoopTask);
+        CoopTask& t = *tasks.back();
+        t.fn = fns[i];
+        t.home = &home;
+        t.stack.reset(new char[kStack]);
+        if (getcontext(&t.ctx) != 0) throw Error(GANMRES_EDEVICE, "getcontext failed");
+        t.ctx.uc_stack.ss_sp = t.stack.get();
+        t.ctx.uc_stack.ss_size = kStack;
+        t.ctx.uc_link = &home;
+        const uintptr_t p = reinterpret_cast<uintptr_t>(&t);
+        makecontext(&t.ctx, reinterpret_cast<void (*)()>(&coop_entry), 2,
+                    static_cast<unsigned>(p & 0xffffffffu), static_cast<unsigned>(p >> 32));
+    }
+    for (;;) {
+        for (auto& tp : tasks)
+            if (tp->state == CoopTask::RUN) {
+                g_coop = tp.get();
+                swapcontext(&home, &tp->ctx);
+                g_coop = nullptr;
+            }
+        int launch = 0, sync = 0, barrier = 0, live = 0;
+        for (auto& tp : tasks) {
+            launch += tp->state == CoopTask::LAUNCH;
+            sync += tp->state == CoopTask::SYNC;
+            barrier += tp->state == CoopTask::BARRIER;
+            live += tp->state != CoopTask::DONE;
+        }
+        if (live == 0) break;
+        if (launch > 0) {
+            // one launch per family (chunks of kMaxGroup classes)
+            std::vector<char> taken(n, 0);
+            for (int i = 0; i < n; ++i) {
+                if (taken[i] || tasks[i]->state != CoopTask::LAUNCH) continue;
+                std::vector<int> fam;
+                for (int j = i; j < n; ++j)
+                    if (!taken[j] && tasks[j]->state == CoopTask::LAUNCH &&
+                        tasks[j]->desc.fam == tasks[i]->desc.fam) {
+                        fam.push_back(j);
+                        taken[j] = 1;
+                    }
+                for (size_t c0 = 0; c0 < fam.size(); c0 += kMaxGroup) {
+                    const int m = static_cast<int>(std::min(fam.size() - c0, size_t(kMaxGroup)));
+                    hipError_t rc;
+                    if (m == 1) {
+                        rc = tasks[fam[c0]]->desc.launch_single(tasks[fam[c0]]->desc, st);
+                    } else {
+                        const LaunchDesc* ds[kMaxGroup];
+                        for (int q = 0; q < m; ++q) ds[q] = &tasks[fam[c0 + q]]->desc;
+                        rc = ds[0]->fam->launch_group(ds, m, st);
+                    }
+                    if (stats) {
+                        stats->submitted += m;
+                        stats->issued += 1;
+                    }
+                    for (int q = 0; q < m; ++q) {
+                        CoopTask& t = *tasks[fam[c0 + q]];
+                        t.state = CoopTask::RUN;
+                        if (rc != hipSuccess) {
+                            t.fail = 1;
+                            t.fail_msg = std::string("kernel launch: ") + hipGetErrorString(rc);
+                        }
+                    }
+                }
+            }
+            continue;
+        }
+        if (sync > 0) {
+            const hipError_t rc = hipStreamSynchronize(st);
+            for (auto& tp : tasks)
+                if (tp->state == CoopTask::SYNC) {
+                    tp->state = CoopTask::RUN;
+                    if (rc != hipSuccess) {
+                        tp->fail = 1;
+                        tp->fail_msg = std::string("hipStreamSynchronize: ") + hipGetErrorString(rc);
+                    }
+                }
+            continue;
+        }
+        // every live task waits at a reduction
+        long long mx = LLONG_MIN, any = 0;
+        for (auto& tp : tasks)
+            if (tp->state == CoopTask::BARRIER) {
+                if (tp->bop == 0) mx = std::max(mx, tp->bval);
+                else any = any || tp->bval != 0;
+            }
+        for (auto& tp : tasks)
+            if (tp->state == CoopTask::BARRIER) {
+                tp->bval = tp->bop == 0 ? mx : any;
+                tp->state = CoopTask::RUN;
+            }
+        (void)barrier;
+    }
+    for (auto& tp : tasks)
+        if (tp->err != GANMRES_OK) throw Error(tp->err, tp->err_msg);
+}
+
+// Synchronisation points and reductions of code that may run as a task.
+static inline void stream_sync(hipStream_t st) {
+    if (CoopTask* t = coop_current()) coop_sync(t);
+    else HIPCHK(hipStreamSynchronize(st));
+}
+static inline void event_sync(hipEvent_t ev) {
+    // under the scheduler a stream synchronisation covers every event
+    if (CoopTask* t = coop_current()) coop_sync(t);
+    else HIPCHK(hipEventSynchronize(ev));
+}
+static inline int group_max(int v) {
+    CoopTask* t = coop_current();
+    return t ? static_cast<int>(coop_reduce(t, v, 0)) : v;
+}
+static inline bool group_any(bool v) {
+    CoopTask* t = coop_current();
+    return t ? coop_reduce(t, v ? 1 : 0, 1) != 0 : v;
+}
 
 // ---- small dense FP64 least squares (host) ----------------------------------
 // Solve M beta = y (M symmetric positive semi-definite, n <= 65): Cholesky,
@@ -440,6 +647,64 @@ class Problem : public ProblemBase {
         HIPCHK(hipMemcpyAsync(m1, m1_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(mstate(0), m0_in, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
+        autotune_tile();
+    }
+
+    // ---- 2-D gather tile autotuner ------------------------------------------
+    // The tile height of the 2-D semi-Lagrangian kernels (points per thread 8,
+    // 4 or 2: tiles of 64 x 32, 64 x 16 or 64 x 8 points) is chosen per grid
+    // (stacked count and size) and element type by timing the gather step of
+    // each variant on this problem's template image with zero displacement
+    // (window tables recorded first, as in a solve), and remembered for the
+    // process.  Small grids gain workgroups from short tiles; large ones keep
+    // the staging of fewer, taller windows.  Every variant gives the same
+    // values: only the work partition changes.
+    int tile_choice = 0;
+    double tile_us[3] = {0.0, 0.0, 0.0};  // per launch, variants 8, 4, 2
+    void autotune_tile() {
+        if (d != 2) return;
+        static std::mutex mu;
+        static std::map<std::tuple<int, int, int, int>, std::pair<int, std::vector<double>>> cache;
+        const auto key = std::make_tuple(dm.n[0], dm.n[1], dm.n[2], (int)sizeof(T));
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            auto it = cache.find(key);
+            if (it != cache.end()) {
+                dm.tile = tile_choice = it->second.first;
+                for (int i = 0; i < 3; ++i) tile_us[i] = it->second.second[i];
+                return;
+            }
+        }
+        constexpr int kReps = 5;
+        const int variants[3] = {8, 4, 2};
+        HIPCHK(hipMemsetAsync(dX, 0, sizeof(T) * d * N, st));
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(hipEventCreate(&e0));
+        HIPCHK(hipEventCreate(&e1));
+        int best = kTile2Default;
+        double best_us = INFINITY;
+        for (int i = 0; i < 3; ++i) {
+            dm.tile = variants[i];
+            HIPCHK(launch_sl_step<T>(dm, m0, dX, nullptr, 0, b, st, tabX, 1));
+            HIPCHK(launch_sl_step<T>(dm, m0, dX, nullptr, 0, b, st, tabX, 0));
+            HIPCHK(hipEventRecord(e0, st));
+            for (int r = 0; r < kReps; ++r) HIPCHK(launch_sl_step<T>(dm, m0, dX, nullptr, 0, b, st, tabX, 0));
+            HIPCHK(hipEventRecord(e1, st));
+            HIPCHK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            tile_us[i] = 1e3 * ms / kReps;
+            if (tile_us[i] < best_us) {
+                best_us = tile_us[i];
+                best = variants[i];
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        dm.tile = tile_choice = best;
+        tabX_ok = false;
+        std::lock_guard<std::mutex> lk(mu);
+        cache[key] = {best, std::vector<double>(tile_us, tile_us + 3)};
     }
 
     ~Problem() override {
@@ -511,7 +776,7 @@ class Problem : public ProblemBase {
     // copy result slot [at, at + n) to the host (synchronises)
     const double* fetch(int at, int n) {
         HIPCHK(hipMemcpyAsync(hres + at, dres + at, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        stream_sync(st);
         return hres + at;
     }
     // scalar and velocity fields as segments (one per stacked problem)
@@ -547,8 +812,10 @@ class Problem : public ProblemBase {
     void set_bounds(const void* v, double um) {
         umax = um;
         umax_of = v;
-        ubound = spread_bound(um * (1.0 + 1e-6));
-        dbound = displacement_bound(um, d);
+        // the classes of a group handle take the largest bound, so that they
+        // select the same kernel variants and their launches merge
+        ubound = group_max(spread_bound(um * (1.0 + 1e-6)));
+        dbound = group_max(displacement_bound(um, d));
     }
 
     // max |u| of a velocity over all problems (reduction + sync)
@@ -577,7 +844,7 @@ class Problem : public ProblemBase {
             HIPCHK(hipMemcpyAsync(hres + R_UMAX, dres + R_UMAX, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(ev_res, st));
             if (!trial) spectrum_of(v);
-            HIPCHK(hipEventSynchronize(ev_res));
+            event_sync(ev_res);
             set_bounds(v, hres[R_UMAX]);
         }
         if (delta) {
@@ -655,7 +922,7 @@ class Problem : public ProblemBase {
     double finish_J(double* mis_out) {
         const int n = reg_from_device ? R_REG + nb : nb;
         HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        stream_sync(st);
         return J_from_host(mis_out);
     }
     // copy the ingredients of J to the host behind an event (see J_from_host)
@@ -794,7 +1061,7 @@ class Problem : public ProblemBase {
     bool J_pending = false;
     double resolve_J() {
         if (!J_pending) return 0.0;
-        HIPCHK(hipEventSynchronize(ev_res));
+        event_sync(ev_res);
         J_pending = false;
         return J_from_host(nullptr);
     }
@@ -861,7 +1128,7 @@ class Problem : public ProblemBase {
         HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT,
                               sizeof(double) * ((keep ? R_CROSS + 2 * nb : R_SMAX + 1) - R_DOT),
                               hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
+        stream_sync(st);
         if (keep) smax = hres[R_SMAX];
         gs_s.resize(nb);
         for (int i = 0; i < nb; ++i) gs_s[i] = cell * hres[R_DOT + i];
@@ -889,7 +1156,7 @@ class Problem : public ProblemBase {
             if (!src) throw Error(GANMRES_ESTATE, "adjoint not kept at this time (checkpoint mode)");
         }
         HIPCHK(hipMemcpyAsync(out, src, sizeof(T) * N, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
+        stream_sync(st);
     }
 
     // ---- Gauss-Newton-Krylov baseline (Appendix A) ---------------------------
@@ -1547,7 +1814,9 @@ class Problem : public ProblemBase {
         std::vector<char> done(nb, 0);
         Jq.assign(nb, 0.0);
         int open = nb;
-        for (int t = 0; t <= p.max_backtracks && open > 0; ++t) {
+        // the classes of a group handle backtrack together until all have
+        // accepted (a class with nothing left to decide launches nothing)
+        for (int t = 0; t <= p.max_backtracks && group_any(open > 0); ++t) {
             std::vector<double> bound(nb, 0.0);
             bool transport = false;
             for (int i = 0; i < nb; ++i) {
@@ -1644,7 +1913,7 @@ class Problem : public ProblemBase {
         run(KC_REDUCE, [&] { return launch_maxabs<T>(Gn, vseg(), partial, dres + R_MAX, st); });
         HIPCHK(hipMemcpyAsync(hres + R_MAX, dres + R_MAX, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
+        stream_sync(st);
         if (J_pending) resolve_J();  // the copy behind ev_res has run
         const std::vector<double>& Jv = Jnew.empty() ? J_s : Jnew;
         const std::vector<double> ginf(hres + R_MAX, hres + R_MAX + nb);
@@ -1803,6 +2072,112 @@ class Problem : public ProblemBase {
     }
 };
 
+// A group handle: batches of 2-D problems of different grid sizes ("size
+// classes", each a stacked batch handle of its own) that run every phase
+// together: the classes execute as cooperative tasks (coop_run) and their
+// launches of one kernel family are issued as one launch.  Velocities,
+// images and per-problem results are the classes' back to back.
+template <typename T>
+class GroupProblem : public ProblemBase {
+   public:
+    std::vector<std::unique_ptr<Problem<T>>> cls;
+    std::vector<size_t> voff, ioff;  // bytes of the velocities / images before class c
+    std::vector<int> poff;           // problems before class c
+    int total = 0;
+    hipStream_t st;
+    CoopStats stats;
+
+    GroupProblem(const ganmres_config& cfg, int nclass, const int* shapes, const int* counts,
+                 const double* alpha, const void* const* m0, const void* const* m1, hipStream_t s)
+        : st(s) {
+        size_t vo = 0, io = 0;
+        for (int c = 0; c < nclass; ++c) {
+            ganmres_config cc = cfg;
+            cc.n[0] = shapes[2 * c];
+            cc.n[1] = shapes[2 * c + 1];
+            cc.n[2] = 1;
+            cls.emplace_back(new Problem<T>(cc, m0[c], m1[c], s, counts[c], alpha ? alpha + total : nullptr));
+            voff.push_back(vo);
+            ioff.push_back(io);
+            poff.push_back(total);
+            const size_t pts = (size_t)counts[c] * cc.n[0] * cc.n[1];
+            vo += 2 * pts * sizeof(T);
+            io += pts * sizeof(T);
+            total += counts[c];
+        }
+    }
+    const void* vp(const void* v, int c) const { return static_cast<const char*>(v) + voff[c]; }
+    void* vp(void* v, int c) const { return static_cast<char*>(v) + voff[c]; }
+
+    // f(c) for every class, the classes' launches merged
+    template <typename F>
+    void each(F&& f) {
+        std::vector<std::function<void()>> fns;
+        for (int c = 0; c < (int)cls.size(); ++c) fns.push_back([&f, c] { f(c); });
+        coop_run(fns, st, &stats);
+    }
+
+    double objective(const void* v, bool keep, double* mismatch) override {
+        std::vector<double> J(cls.size()), M(cls.size());
+        each([&](int c) { J[c] = cls[c]->objective(vp(v, c), keep, &M[c]); });
+        double jt = 0.0, mt = 0.0;
+        for (size_t c = 0; c < cls.size(); ++c) {
+            jt += J[c];
+            mt += M[c];
+        }
+        if (mismatch) *mismatch = mt;
+        return jt;
+    }
+    double gradient(const void* v, void* g, bool reuse) override {
+        std::vector<double> J(cls.size());
+        each([&](int c) { J[c] = cls[c]->gradient(vp(v, c), vp(g, c), reuse); });
+        double jt = 0.0;
+        for (double x : J) jt += x;
+        return jt;
+    }
+    double precond(const void* g, void* s) override {
+        std::vector<double> G(cls.size());
+        each([&](int c) { G[c] = cls[c]->precond(vp(g, c), vp(s, c)); });
+        double t = 0.0;
+        for (double x : G) t += x;
+        return t;
+    }
+    void step(const ganmres_solver_params& p, void* v, ganmres_step_info* info) override {
+        if (p.accel == GANMRES_ACCEL_NK)
+            throw Error(GANMRES_EINVAL, "the Newton-Krylov baseline runs on single problems");
+        each([&](int c) { cls[c]->step(p, vp(v, c), info + poff[c]); });
+    }
+    int count() const override { return total; }
+    void deformation(const void* v, void* det, double* st4) override {
+        each([&](int c) {
+            cls[c]->deformation(vp(v, c), det ? static_cast<char*>(det) + ioff[c] : nullptr,
+                                st4 + 4 * poff[c]);
+        });
+    }
+    void hessian_matvec(const void*, const void*, void*) override {
+        throw Error(GANMRES_EINVAL, "the Gauss-Newton Hessian needs a single problem");
+    }
+    void newton_precond(int, const void*, const void*, void*) override {
+        throw Error(GANMRES_EINVAL, "the Newton-step preconditioners need a single problem");
+    }
+    void values(double* J, double* mis) const override {
+        for (size_t c = 0; c < cls.size(); ++c)
+            cls[c]->values(J ? J + poff[c] : nullptr, mis ? mis + poff[c] : nullptr);
+    }
+    void reset() override {
+        for (auto& p : cls) p->reset();
+    }
+    void get_field(int which, int j, void* out) override {
+        each([&](int c) { cls[c]->get_field(which, j, static_cast<char*>(out) + ioff[c]); });
+    }
+    long long workspace_bytes() const override {
+        long long b = 0;
+        for (auto& p : cls) b += p->workspace_bytes();
+        return b;
+    }
+    void timing_flush() override {}
+};
+
 }  // namespace gan
 
 struct ganmres_handle {
@@ -1874,7 +2249,96 @@ static int create_impl(const ganmres_config* cfg, int count, const double* alpha
     return GANMRES_OK;
 }
 
+static int create_group_impl(const ganmres_config* cfg, int nclass, const int* shapes,
+                             const int* counts, const double* alpha, const void* const* m0,
+                             const void* const* m1, void* stream, ganmres_handle** out) {
+    if (!cfg || !shapes || !counts || !m0 || !m1 || !out) {
+        g_create_error = "null argument";
+        return GANMRES_EINVAL;
+    }
+    *out = nullptr;
+    std::string why;
+    if (cfg->dim != 2) why = "a group holds 2-D problems";
+    if (why.empty() && (nclass < 1 || nclass > gan::kMaxClasses)) why = "nclass must be in [1, 16]";
+    int total = 0;
+    for (int c = 0; why.empty() && c < nclass; ++c) {
+        if (counts[c] < 1 || counts[c] > gan::kMaxSeg) why = "every class count must be in [1, 64]";
+        if (!m0[c] || !m1[c]) why = "null image";
+        ganmres_config cc = *cfg;
+        cc.n[0] = shapes[2 * c];
+        cc.n[1] = shapes[2 * c + 1];
+        cc.n[2] = 1;
+        const std::string cw = gan::config_error(cc);
+        if (why.empty() && !cw.empty()) why = cw;
+        total += counts[c];
+    }
+    for (int i = 0; why.empty() && alpha && i < total; ++i)
+        if (!(alpha[i] > 0.0)) why = "alpha must be > 0";
+    if (!why.empty()) {
+        g_create_error = why;
+        return GANMRES_EINVAL;
+    }
+    auto* h = new ganmres_handle;
+    h->dtype = cfg->dtype;
+    const int rc = guarded(h, [&] {
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        if (cfg->dtype == GANMRES_F32)
+            h->impl.reset(new gan::GroupProblem<float>(*cfg, nclass, shapes, counts, alpha, m0, m1, st));
+        else
+            h->impl.reset(new gan::GroupProblem<double>(*cfg, nclass, shapes, counts, alpha, m0, m1, st));
+    });
+    if (rc != GANMRES_OK) {
+        g_create_error = h->err;
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return GANMRES_OK;
+}
+
 extern "C" {
+
+int ganmres_create_group(const ganmres_config* cfg, int nclass, const int* shapes,
+                         const int* counts, const double* alpha, const void* const* m0,
+                         const void* const* m1, void* stream, ganmres_handle** out) {
+    return create_group_impl(cfg, nclass, shapes, counts, alpha, m0, m1, stream, out);
+}
+
+int ganmres_tile_autotune(const ganmres_handle* h, int cls, int* points_per_thread, double* us) {
+    if (!h || !points_per_thread) return GANMRES_EINVAL;
+    auto report = [&](auto* p) {
+        *points_per_thread = p->tile_choice;
+        if (us)
+            for (int i = 0; i < 3; ++i) us[i] = p->tile_us[i];
+    };
+    if (auto* g = dynamic_cast<const gan::GroupProblem<float>*>(h->impl.get())) {
+        if (cls < 0 || cls >= (int)g->cls.size()) return GANMRES_EINVAL;
+        report(g->cls[cls].get());
+    } else if (auto* g = dynamic_cast<const gan::GroupProblem<double>*>(h->impl.get())) {
+        if (cls < 0 || cls >= (int)g->cls.size()) return GANMRES_EINVAL;
+        report(g->cls[cls].get());
+    } else if (auto* p = dynamic_cast<const gan::Problem<float>*>(h->impl.get())) {
+        if (cls != 0) return GANMRES_EINVAL;
+        report(p);
+    } else if (auto* p = dynamic_cast<const gan::Problem<double>*>(h->impl.get())) {
+        if (cls != 0) return GANMRES_EINVAL;
+        report(p);
+    } else {
+        return GANMRES_EINVAL;
+    }
+    return GANMRES_OK;
+}
+
+int ganmres_group_launches(const ganmres_handle* h, long long* submitted, long long* issued) {
+    if (!h || !submitted || !issued) return GANMRES_EINVAL;
+    const gan::CoopStats* s = nullptr;
+    if (auto* g = dynamic_cast<const gan::GroupProblem<float>*>(h->impl.get())) s = &g->stats;
+    if (auto* g = dynamic_cast<const gan::GroupProblem<double>*>(h->impl.get())) s = &g->stats;
+    if (!s) return GANMRES_EINVAL;
+    *submitted = s->submitted;
+    *issued = s->issued;
+    return GANMRES_OK;
+}
 
 int ganmres_create(const ganmres_config* cfg, const void* m0, const void* m1, void* stream,
                    ganmres_handle** out) {

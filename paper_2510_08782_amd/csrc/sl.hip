@@ -24,6 +24,7 @@
 #include <cmath>
 
 #include "launch.hpp"
+#include "group.hpp"
 #include "reduce.hpp"
 
 namespace gan {
@@ -116,10 +117,13 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
 }
 
 // ---- tile geometry -----------------------------------------------------------
-// 3-D: threads (32 x 8), each owns TZ points along z.  2-D: threads (64 x 4),
-// each owns 8 points along y (tile 64 x 32).  S is the capacity of the staged
-// region: up to S cells of spread of the displacement floors per axis.
-template <typename T_, int DIM_, int S_, int TZ_ = (sizeof(T_) == 4 ? 2 : 4)>
+// 3-D: threads (32 x 8), each owns P = TZ points along z.  2-D: threads
+// (64 x 4), each owns P points along y (tile 64 x 4P; P = 8, 4 or 2, the
+// variant chosen per grid size by the tile autotuner, see Dims::tile).  S is
+// the capacity of the staged region: up to S cells of spread of the
+// displacement floors per axis.
+template <typename T_, int DIM_, int S_,
+          int P_ = (DIM_ == 3 ? (sizeof(T_) == 4 ? 2 : 4) : kTile2Default)>
 struct Tile;
 template <typename T_, int S_, int TZ_>
 struct Tile<T_, 3, S_, TZ_> {
@@ -135,16 +139,16 @@ struct Tile<T_, 3, S_, TZ_> {
     static_assert(RX <= PX, "window wider than the row pitch");
     static constexpr int PTS = TZ;  // points per thread
 };
-template <typename T_, int S_, int TZ_>
-struct Tile<T_, 2, S_, TZ_> {
+template <typename T_, int S_, int P_>
+struct Tile<T_, 2, S_, P_> {
     using T = T_;
     static constexpr int DIM = 2;
-    static constexpr int TX = 64, TY = 32, TZ = 1;
+    static constexpr int TX = 64, TY = 4 * P_, TZ = 1;
     static constexpr int S = S_;
     static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = 1;
     static constexpr int PX = RX;  // a wavefront reads one row
     static constexpr int PZ = PX * RY;
-    static constexpr int PTS = 8;
+    static constexpr int PTS = P_;
 };
 
 template <class C>
@@ -413,12 +417,12 @@ template <class C>
 struct PointMap {
     int x0, y0, z0, t;
     bool valid;
-    __device__ PointMap(const Dims& dm) {
+    __device__ PointMap(const Dims& dm, const Blk& bk) {
         const int ntx = (dm.n[2] + C::TX - 1) / C::TX;
         const int nty = (dm.n[1] + C::TY - 1) / C::TY;
         const int T = tile_count<C>(dm);
         const int per = (T + kXcds - 1) / kXcds;
-        t = (blockIdx.x % kXcds) * per + blockIdx.x / kXcds;
+        t = (bk.x % kXcds) * per + bk.x / kXcds;
         valid = t < T;
         x0 = (t % ntx) * C::TX;
         y0 = ((t / ntx) % nty) * C::TY;
@@ -469,87 +473,109 @@ __device__ inline T step_epilogue(T r, const T* __restrict__ src, const T* __res
 // the source is in flight while the displacements load.  With table_write = 1
 // (the first gather over a new field) the LDS kernel reduces its windows as
 // without a table and records them there.
+template <typename T>
+struct SlStepArgs {
+    Dims dm;
+    const T* src;
+    const T* disp;
+    const T* fac;
+    T ht;
+    T sgn;
+    T* out;
+    int* table;
+    int table_write;
+};
 template <class C, int EPI, bool LDS>
-__global__ void __launch_bounds__(kThreads) sl_step_kernel(
-    Dims dm, const typename C::T* __restrict__ src, const typename C::T* __restrict__ disp,
-    const typename C::T* __restrict__ fac, typename C::T ht, typename C::T sgn,
-    typename C::T* __restrict__ out, int* __restrict__ table, int table_write) {
-    using T = typename C::T;
-    constexpr int DIM = C::DIM;
-    extern __shared__ double2 sl_smem[];
-    T* lds = reinterpret_cast<T*>(sl_smem);
-    __shared__ int red[6 * (kThreads / 64)];
-    const PointMap<C> pm(dm);
-    if (!pm.valid) return;
-    Window win{};
-    const bool use_table = table && !table_write;
-    if (use_table) {
-        const int* e = table + (long long)pm.t * kWinInts;
-        const int m[3] = {e[0], e[1], e[2]}, M[3] = {e[3], e[4], e[5]};
-        win = window_from<C>(m, M);
-        if (win.lds != LDS) return;
-        if constexpr (LDS) stage<C, false>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
-    }
-    const long long N = dm.N;
-    // displacements of the thread's points and their floor ranges
-    T d0[C::PTS], d1[C::PTS], d2[C::PTS];
-    long long lin[C::PTS];
-    bool in[C::PTS];
-    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        in[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
-        lin[k] = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
-        // every lane loads (a point outside the grid reads element 0), so
-        // that the loads of all points are in flight together
-        const long long lc = in[k] ? lin[k] : 0;
-        if constexpr (DIM == 3) {
-            d0[k] = disp[lc];
-            d1[k] = disp[N + lc];
-            d2[k] = disp[2 * N + lc];
-        } else {
-            d0[k] = T(0);
-            d1[k] = disp[lc];
-            d2[k] = disp[N + lc];
+struct SlStepBody {
+    static constexpr int kBlock = kThreads;
+    using Args = SlStepArgs<typename C::T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const typename C::T* __restrict__ src = args_.src;
+        const typename C::T* __restrict__ disp = args_.disp;
+        const typename C::T* __restrict__ fac = args_.fac;
+        typename C::T ht = args_.ht;
+        typename C::T sgn = args_.sgn;
+        typename C::T* __restrict__ out = args_.out;
+        int* __restrict__ table = args_.table;
+        int table_write = args_.table_write;
+        using T = typename C::T;
+        constexpr int DIM = C::DIM;
+        extern __shared__ double2 sl_smem[];
+        T* lds = reinterpret_cast<T*>(sl_smem);
+        __shared__ int red[6 * (kThreads / 64)];
+        const PointMap<C> pm(dm, bk);
+        if (!pm.valid) return;
+        Window win{};
+        const bool use_table = table && !table_write;
+        if (use_table) {
+            const int* e = table + (long long)pm.t * kWinInts;
+            const int m[3] = {e[0], e[1], e[2]}, M[3] = {e[3], e[4], e[5]};
+            win = window_from<C>(m, M);
+            if (win.lds != LDS) return;
+            if constexpr (LDS) stage<C, false>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
         }
-    }
-    if (!use_table) {
-#pragma unroll
+        const long long N = dm.N;
+        // displacements of the thread's points and their floor ranges
+        T d0[C::PTS], d1[C::PTS], d2[C::PTS];
+        long long lin[C::PTS];
+        bool in[C::PTS];
+        int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    #pragma unroll
         for (int k = 0; k < C::PTS; ++k) {
-            const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
-#pragma unroll
-            for (int q = 0; q < 3; ++q) {
-                fmn[q] = in[k] ? min(fmn[q], f[q]) : fmn[q];
-                fmx[q] = in[k] ? max(fmx[q], f[q]) : fmx[q];
+            int lx, ly, lz;
+            pm.local(k, lx, ly, lz);
+            const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+            in[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+            lin[k] = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+            // every lane loads (a point outside the grid reads element 0), so
+            // that the loads of all points are in flight together
+            const long long lc = in[k] ? lin[k] : 0;
+            if constexpr (DIM == 3) {
+                d0[k] = disp[lc];
+                d1[k] = disp[N + lc];
+                d2[k] = disp[2 * N + lc];
+            } else {
+                d0[k] = T(0);
+                d1[k] = disp[lc];
+                d2[k] = disp[N + lc];
             }
         }
+        if (!use_table) {
+    #pragma unroll
+            for (int k = 0; k < C::PTS; ++k) {
+                const int f[3] = {disp_floor(d2[k]), disp_floor(d1[k]), disp_floor(d0[k])};
+    #pragma unroll
+                for (int q = 0; q < 3; ++q) {
+                    fmn[q] = in[k] ? min(fmn[q], f[q]) : fmn[q];
+                    fmx[q] = in[k] ? max(fmx[q], f[q]) : fmx[q];
+                }
+            }
+        }
+        if (!use_table) {
+            win = tile_window<C>(fmn, fmx, red,
+                                 (LDS && table) ? table + (long long)pm.t * kWinInts : nullptr);
+            if (win.lds != LDS) return;
+            if constexpr (LDS) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
+        } else if constexpr (LDS) {
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
+    #pragma unroll
+        for (int k = 0; k < C::PTS; ++k) {
+            if (!in[k]) continue;
+            int lx, ly, lz;
+            pm.local(k, lx, ly, lz);
+            T r;
+            if constexpr (LDS)
+                r = gather_lds<C>(lds, win, lx, ly, lz, d0[k], d1[k], d2[k]);
+            else
+                r = gather_global<T, DIM>(dm, src, pm.z0 + lz, pm.y0 + ly, pm.x0 + lx, d0[k], d1[k],
+                                          d2[k]);
+            out[lin[k]] = step_epilogue<T, EPI>(r, src, fac, lin[k], ht, sgn);
+        }
     }
-    if (!use_table) {
-        win = tile_window<C>(fmn, fmx, red,
-                             (LDS && table) ? table + (long long)pm.t * kWinInts : nullptr);
-        if (win.lds != LDS) return;
-        if constexpr (LDS) stage<C>(dm, src, lds, pm.x0, pm.y0, pm.z0, win);
-    } else if constexpr (LDS) {
-        __builtin_amdgcn_s_waitcnt(0);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-        if (!in[k]) continue;
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        T r;
-        if constexpr (LDS)
-            r = gather_lds<C>(lds, win, lx, ly, lz, d0[k], d1[k], d2[k]);
-        else
-            r = gather_global<T, DIM>(dm, src, pm.z0 + lz, pm.y0 + ly, pm.x0 + lx, d0[k], d1[k],
-                                      d2[k]);
-        out[lin[k]] = step_epilogue<T, EPI>(r, src, fac, lin[k], ht, sgn);
-    }
-}
+};
 
 // ---- characteristics -------------------------------------------------------------
 // dX = -(u + I[u](i - u)) / 2 (state, +v) and dY = (u + I[u](i + u)) / 2
@@ -557,216 +583,274 @@ __global__ void __launch_bounds__(kThreads) sl_step_kernel(
 // grid point, so the window is known before any staging; component c of v is
 // then staged in LDS in turn.  With both directions the window covers both
 // sets of predictor points.
+template <typename T>
+struct CharacteristicsArgs {
+    Dims dm;
+    const T* v;
+    T s0;
+    T s1;
+    T s2;
+    T* dX;
+    T* dY;
+};
 template <class C, bool DOX, bool DOY, bool LDS>
-__global__ void __launch_bounds__(kThreads) characteristics_kernel(
-    Dims dm, const typename C::T* __restrict__ v, typename C::T s0, typename C::T s1,
-    typename C::T s2, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
-    using T = typename C::T;
-    constexpr int DIM = C::DIM;
-    extern __shared__ double2 sl_smem[];
-    T* lds = reinterpret_cast<T*>(sl_smem);
-    __shared__ int red[6 * (kThreads / 64)];
-    const PointMap<C> pm(dm);
-    if (!pm.valid) return;
-    const long long N = dm.N;
-    const T s[3] = {s0, s1, s2};
-    // u at the thread's points, all loads in flight together (a point
-    // outside the grid reads element 0 and is masked)
-    T u[C::PTS][DIM];
-    bool inp[C::PTS];
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
-        const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) u[k][c] = v[c * N + lc];
-    }
-    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) {
-            u[k][c] = inp[k] ? u[k][c] * s[c] : T(0);
-            const int q = DIM - 1 - c;  // axis slot: x, y, z
-            if (DOX) {
-                const int f = disp_floor(-u[k][c]);
-                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
-                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
-            }
-            if (DOY) {
-                const int f = disp_floor(u[k][c]);
-                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
-                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
-            }
-        }
-    }
-    const Window win = tile_window<C>(fmn, fmx, red);
-    if (win.lds != LDS) return;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        const T* vc = v + c * N;
-        if constexpr (LDS) {
-            if (c > 0) __syncthreads();
-            stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0, win);
-        }
-#pragma unroll
+struct CharacteristicsBody {
+    static constexpr int kBlock = kThreads;
+    using Args = CharacteristicsArgs<typename C::T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const typename C::T* __restrict__ v = args_.v;
+        typename C::T s0 = args_.s0;
+        typename C::T s1 = args_.s1;
+        typename C::T s2 = args_.s2;
+        typename C::T* __restrict__ dX = args_.dX;
+        typename C::T* __restrict__ dY = args_.dY;
+        using T = typename C::T;
+        constexpr int DIM = C::DIM;
+        extern __shared__ double2 sl_smem[];
+        T* lds = reinterpret_cast<T*>(sl_smem);
+        __shared__ int red[6 * (kThreads / 64)];
+        const PointMap<C> pm(dm, bk);
+        if (!pm.valid) return;
+        const long long N = dm.N;
+        const T s[3] = {s0, s1, s2};
+        // u at the thread's points, all loads in flight together (a point
+        // outside the grid reads element 0 and is masked)
+        T u[C::PTS][DIM];
+        bool inp[C::PTS];
+    #pragma unroll
         for (int k = 0; k < C::PTS; ++k) {
-            if (!inp[k]) continue;
             int lx, ly, lz;
             pm.local(k, lx, ly, lz);
             const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-            const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
-            const T e0 = DIM == 3 ? u[k][0] : T(0), e1 = DIM == 3 ? u[k][1] : u[k][0];
-            const T e2 = DIM == 3 ? u[k][2] : u[k][1];
-            if (DOX) {
-                const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, -e0, -e1, -e2)
-                                 : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
-                dX[c * N + lin] = T(-0.5) * (u[k][c] + s[c] * iv);
+            inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+            const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
+    #pragma unroll
+            for (int c = 0; c < DIM; ++c) u[k][c] = v[c * N + lc];
+        }
+        int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+    #pragma unroll
+        for (int k = 0; k < C::PTS; ++k) {
+    #pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                u[k][c] = inp[k] ? u[k][c] * s[c] : T(0);
+                const int q = DIM - 1 - c;  // axis slot: x, y, z
+                if (DOX) {
+                    const int f = disp_floor(-u[k][c]);
+                    fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                    fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                }
+                if (DOY) {
+                    const int f = disp_floor(u[k][c]);
+                    fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                    fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                }
             }
-            if (DOY) {
-                const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, e0, e1, e2)
-                                 : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
-                dY[c * N + lin] = T(0.5) * (u[k][c] + s[c] * iv);
+        }
+        const Window win = tile_window<C>(fmn, fmx, red);
+        if (win.lds != LDS) return;
+    #pragma unroll
+        for (int c = 0; c < DIM; ++c) {
+            const T* vc = v + c * N;
+            if constexpr (LDS) {
+                if (c > 0) __syncthreads();
+                stage<C>(dm, vc, lds, pm.x0, pm.y0, pm.z0, win);
+            }
+    #pragma unroll
+            for (int k = 0; k < C::PTS; ++k) {
+                if (!inp[k]) continue;
+                int lx, ly, lz;
+                pm.local(k, lx, ly, lz);
+                const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+                const long long lin = ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2;
+                const T e0 = DIM == 3 ? u[k][0] : T(0), e1 = DIM == 3 ? u[k][1] : u[k][0];
+                const T e2 = DIM == 3 ? u[k][2] : u[k][1];
+                if (DOX) {
+                    const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, -e0, -e1, -e2)
+                                     : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
+                    dX[c * N + lin] = T(-0.5) * (u[k][c] + s[c] * iv);
+                }
+                if (DOY) {
+                    const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, e0, e1, e2)
+                                     : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
+                    dY[c * N + lin] = T(0.5) * (u[k][c] + s[c] * iv);
+                }
             }
         }
     }
-}
+};
 
 // Characteristics with every component of v staged at once (DIM windows in
 // LDS): the stencil of a predictor point (weights, first tap) is computed
 // once and serves all DIM components, and with both directions one staging
 // serves X and Y.  Tiles that do not fit are left to
 // characteristics_kernel<C, DOX, DOY, false>.
+template <typename T>
+struct CharacteristicsAllArgs {
+    Dims dm;
+    const T* v;
+    T s0;
+    T s1;
+    T s2;
+    T* dX;
+    T* dY;
+};
 template <class C, bool DOX, bool DOY>
-__global__ void __launch_bounds__(kThreads) characteristics_all_kernel(
-    Dims dm, const typename C::T* __restrict__ v, typename C::T s0, typename C::T s1,
-    typename C::T s2, typename C::T* __restrict__ dX, typename C::T* __restrict__ dY) {
-    using T = typename C::T;
-    constexpr int DIM = C::DIM;
-    constexpr int PLANE = C::PZ * C::RZ;  // elements per staged component
-    extern __shared__ double2 sl_smem[];
-    T* lds = reinterpret_cast<T*>(sl_smem);
-    __shared__ int red[6 * (kThreads / 64)];
-    const PointMap<C> pm(dm);
-    if (!pm.valid) return;
-    const long long N = dm.N;
-    const T s[3] = {s0, s1, s2};
-    int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
-    // every lane loads (a point outside the grid reads element 0), so that
-    // the loads of all points are in flight together
-    T ev[C::PTS][DIM];
-    bool inp[C::PTS];
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
-        inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
-        const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) ev[k][c] = v[c * N + lc];
-    }
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-#pragma unroll
+struct CharacteristicsAllBody {
+    static constexpr int kBlock = kThreads;
+    using Args = CharacteristicsAllArgs<typename C::T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const typename C::T* __restrict__ v = args_.v;
+        typename C::T s0 = args_.s0;
+        typename C::T s1 = args_.s1;
+        typename C::T s2 = args_.s2;
+        typename C::T* __restrict__ dX = args_.dX;
+        typename C::T* __restrict__ dY = args_.dY;
+        using T = typename C::T;
+        constexpr int DIM = C::DIM;
+        constexpr int PLANE = C::PZ * C::RZ;  // elements per staged component
+        extern __shared__ double2 sl_smem[];
+        T* lds = reinterpret_cast<T*>(sl_smem);
+        __shared__ int red[6 * (kThreads / 64)];
+        const PointMap<C> pm(dm, bk);
+        if (!pm.valid) return;
+        const long long N = dm.N;
+        const T s[3] = {s0, s1, s2};
+        int fmn[3] = {1 << 30, 1 << 30, 1 << 30}, fmx[3] = {-(1 << 30), -(1 << 30), -(1 << 30)};
+        // every lane loads (a point outside the grid reads element 0), so that
+        // the loads of all points are in flight together
+        T ev[C::PTS][DIM];
+        bool inp[C::PTS];
+    #pragma unroll
+        for (int k = 0; k < C::PTS; ++k) {
+            int lx, ly, lz;
+            pm.local(k, lx, ly, lz);
+            const int i2 = pm.x0 + lx, i1 = pm.y0 + ly, i0 = pm.z0 + lz;
+            inp[k] = i2 < dm.n[2] && i1 < dm.n[1] && i0 < dm.n[0];
+            const long long lc = inp[k] ? ((long long)i0 * dm.n[1] + i1) * dm.n[2] + i2 : 0;
+    #pragma unroll
+            for (int c = 0; c < DIM; ++c) ev[k][c] = v[c * N + lc];
+        }
+    #pragma unroll
+        for (int k = 0; k < C::PTS; ++k) {
+    #pragma unroll
+            for (int c = 0; c < DIM; ++c) {
+                const T e = ev[k][c] * s[c];
+                const int q = DIM - 1 - c;  // axis slot: x, y, z
+                if (DOX) {
+                    const int f = disp_floor(-e);
+                    fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                    fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                }
+                if (DOY) {
+                    const int f = disp_floor(e);
+                    fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
+                    fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                }
+            }
+        }
+        const Window win = tile_window<C>(fmn, fmx, red);
+        if (!win.lds) return;
+    #pragma unroll
         for (int c = 0; c < DIM; ++c) {
-            const T e = ev[k][c] * s[c];
-            const int q = DIM - 1 - c;  // axis slot: x, y, z
+            if (c + 1 < DIM)
+                stage<C, false>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
+            else
+                stage<C, true>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
+        }
+    #pragma unroll
+        for (int k = 0; k < C::PTS; ++k) {
+            if (!inp[k]) continue;
+            int lx, ly, lz;
+            pm.local(k, lx, ly, lz);
+            const long long lin =
+                ((long long)(pm.z0 + lz) * dm.n[1] + (pm.y0 + ly)) * dm.n[2] + (pm.x0 + lx);
+            T u[DIM];
+    #pragma unroll
+            for (int c = 0; c < DIM; ++c) u[c] = ev[k][c] * s[c];
+            const T e0 = DIM == 3 ? u[0] : T(0), e1 = DIM == 3 ? u[1] : u[0];
+            const T e2 = DIM == 3 ? u[2] : u[1];
             if (DOX) {
-                const int f = disp_floor(-e);
-                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
-                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, -e0, -e1, -e2);
+    #pragma unroll
+                for (int c = 0; c < DIM; ++c)
+                    dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
             }
             if (DOY) {
-                const int f = disp_floor(e);
-                fmn[q] = inp[k] ? min(fmn[q], f) : fmn[q];
-                fmx[q] = inp[k] ? max(fmx[q], f) : fmx[q];
+                const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, e0, e1, e2);
+    #pragma unroll
+                for (int c = 0; c < DIM; ++c)
+                    dY[c * N + lin] = T(0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
             }
         }
     }
-    const Window win = tile_window<C>(fmn, fmx, red);
-    if (!win.lds) return;
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        if (c + 1 < DIM)
-            stage<C, false>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
-        else
-            stage<C, true>(dm, v + c * N, lds + c * PLANE, pm.x0, pm.y0, pm.z0, win);
-    }
-#pragma unroll
-    for (int k = 0; k < C::PTS; ++k) {
-        if (!inp[k]) continue;
-        int lx, ly, lz;
-        pm.local(k, lx, ly, lz);
-        const long long lin =
-            ((long long)(pm.z0 + lz) * dm.n[1] + (pm.y0 + ly)) * dm.n[2] + (pm.x0 + lx);
-        T u[DIM];
-#pragma unroll
-        for (int c = 0; c < DIM; ++c) u[c] = ev[k][c] * s[c];
-        const T e0 = DIM == 3 ? u[0] : T(0), e1 = DIM == 3 ? u[1] : u[0];
-        const T e2 = DIM == 3 ? u[2] : u[1];
-        if (DOX) {
-            const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, -e0, -e1, -e2);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c)
-                dX[c * N + lin] = T(-0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
-        }
-        if (DOY) {
-            const Stencil<T> st = lds_stencil<C>(win, lx, ly, lz, e0, e1, e2);
-#pragma unroll
-            for (int c = 0; c < DIM; ++c)
-                dY[c * N + lin] = T(0.5) * (u[c] + s[c] * lds_interp<C>(lds + c * PLANE, st));
-        }
-    }
-}
+};
 
 // max_c max_i |s_c v_c(i)| (NaN/inf counted as 1e30): FP64 block partials
 template <typename T>
-__global__ void __launch_bounds__(kThreads) velocity_max_kernel(const T* __restrict__ v,
-                                                                long long N, int dim, double s0,
-                                                                double s1, double s2, int vec,
-                                                                double* __restrict__ partial) {
-    __shared__ double sh[kThreads / 64];
-    const double s[3] = {s0, s1, s2};
-    double m = 0.0;
-    bool bad = false;
-    constexpr int W = 16 / (int)sizeof(T);
-    struct alignas(16) V {
-        T x[W];
-    };
-    for (int c = 0; c < dim; ++c) {
-        // max |v_c| in the field's type, scaled once (s_c > 0); with vec every
-        // thread moves 16 bytes at a time
-        T mc = T(0);
-        if (vec) {
-            const V* row = reinterpret_cast<const V*>(v + c * N);
-            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N / W;
-                 i += (long long)gridDim.x * blockDim.x) {
-                const V q = row[i];
-#pragma unroll
-                for (int w = 0; w < W; ++w) {
-                    const T a = fabs(q.x[w]);
+struct VelocityMaxArgs {
+    const T* v;
+    long long N;
+    int dim;
+    double s0;
+    double s1;
+    double s2;
+    int vec;
+    double* partial;
+};
+template <typename T>
+struct VelocityMaxBody {
+    static constexpr int kBlock = kThreads;
+    using Args = VelocityMaxArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const T* __restrict__ v = args_.v;
+        long long N = args_.N;
+        int dim = args_.dim;
+        double s0 = args_.s0;
+        double s1 = args_.s1;
+        double s2 = args_.s2;
+        int vec = args_.vec;
+        double* __restrict__ partial = args_.partial;
+        __shared__ double sh[kThreads / 64];
+        const double s[3] = {s0, s1, s2};
+        double m = 0.0;
+        bool bad = false;
+        constexpr int W = 16 / (int)sizeof(T);
+        struct alignas(16) V {
+            T x[W];
+        };
+        for (int c = 0; c < dim; ++c) {
+            // max |v_c| in the field's type, scaled once (s_c > 0); with vec every
+            // thread moves 16 bytes at a time
+            T mc = T(0);
+            if (vec) {
+                const V* row = reinterpret_cast<const V*>(v + c * N);
+                for (long long i = bk.x * (long long)blockDim.x + threadIdx.x; i < N / W;
+                     i += (long long)bk.gx * blockDim.x) {
+                    const V q = row[i];
+    #pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const T a = fabs(q.x[w]);
+                        bad = bad || !(a == a);
+                        mc = fmax(mc, a);
+                    }
+                }
+            } else {
+                for (long long i = bk.x * (long long)blockDim.x + threadIdx.x; i < N;
+                     i += (long long)bk.gx * blockDim.x) {
+                    const T a = fabs(v[c * N + i]);
                     bad = bad || !(a == a);
                     mc = fmax(mc, a);
                 }
             }
-        } else {
-            for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
-                 i += (long long)gridDim.x * blockDim.x) {
-                const T a = fabs(v[c * N + i]);
-                bad = bad || !(a == a);
-                mc = fmax(mc, a);
-            }
+            m = fmax(m, double(mc) * s[c]);
         }
-        m = fmax(m, double(mc) * s[c]);
+        if (bad || !(m <= 1.0e30)) m = 1.0e30;
+        const double r = block_reduce<true>(m, sh);
+        if (threadIdx.x == 0) partial[bk.x] = r;
     }
-    if (bad || !(m <= 1.0e30)) m = 1.0e30;
-    const double r = block_reduce<true>(m, sh);
-    if (threadIdx.x == 0) partial[blockIdx.x] = r;
-}
+};
 
 // Variant choice from a bound on the spread of the displacement floors over
 // the field (cells; a displacement bound B gives floor(B) + ceil(B), which is
@@ -781,29 +865,78 @@ int pick_capacity(int spread) {
     return spread <= 2 ? 2 : (spread <= 3 ? 3 : 8);
 }
 
+// Bodies of merged 2-D launches: classes of a group handle may run different
+// tile variants (Dims::tile); the variant of each class is dispatched here.
+template <typename F>
+__device__ __forceinline__ void with_tile_dev(int tile, F&& f) {
+    switch (tile) {
+        case 2: f(std::integral_constant<int, 2>{}); break;
+        case 4: f(std::integral_constant<int, 4>{}); break;
+        default: f(std::integral_constant<int, 8>{}); break;
+    }
+}
+template <typename T, int S, int EPI, bool LDS>
+struct SlStepAnyBody {
+    static constexpr int kBlock = kThreads;
+    using Args = SlStepArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_tile_dev(a.dm.tile, [&](auto p) __attribute__((always_inline)) {
+            SlStepBody<Tile<T, 2, S, decltype(p)::value>, EPI, LDS>::run(a, bk);
+        });
+    }
+};
+template <typename T, int S, bool DOX, bool DOY, bool LDS>
+struct CharacteristicsAnyBody {
+    static constexpr int kBlock = kThreads;
+    using Args = CharacteristicsArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_tile_dev(a.dm.tile, [&](auto p) __attribute__((always_inline)) {
+            CharacteristicsBody<Tile<T, 2, S, decltype(p)::value>, DOX, DOY, LDS>::run(a, bk);
+        });
+    }
+};
+template <typename T, int S, bool DOX, bool DOY>
+struct CharacteristicsAllAnyBody {
+    static constexpr int kBlock = kThreads;
+    using Args = CharacteristicsAllArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_tile_dev(a.dm.tile, [&](auto p) __attribute__((always_inline)) {
+            CharacteristicsAllBody<Tile<T, 2, S, decltype(p)::value>, DOX, DOY>::run(a, bk);
+        });
+    }
+};
+// The merged family of a tile: its variant-dispatching body in 2-D, the
+// tile's own body in 3-D (one variant per capacity).
+template <class C, class Body, class AnyBody>
+using TileFamily = typename std::conditional<C::DIM == 2, AnyBody, Body>::type;
+
+template <class C, bool DOX, bool DOY, bool LDS>
+void char_submit(const Dims& dm, size_t lds, hipStream_t st, const CharacteristicsArgs<typename C::T>& a) {
+    using B = CharacteristicsBody<C, DOX, DOY, LDS>;
+    submit<B, TileFamily<C, B, CharacteristicsAnyBody<typename C::T, C::S, DOX, DOY, LDS>>>(
+        dim3(tile_blocks<C>(dm)), lds, st, a);
+}
+
 template <class C, bool DOX, bool DOY>
 void char_launch(const Dims& dm, const typename C::T* v, const double* s, int spread,
                  typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
-    const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
-    characteristics_kernel<C, DOX, DOY, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-        dm, v, T(s[0]), T(s[1]), s2, dX, dY);
-    if (spread > C::S)
-        characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
-            dm, v, T(s[0]), T(s[1]), s2, dX, dY);
+    const CharacteristicsArgs<T> a{dm, v, T(s[0]), T(s[1]), T(C::DIM == 3 ? s[2] : 0.0), dX, dY};
+    char_submit<C, DOX, DOY, true>(dm, tile_lds_bytes<C>(), st, a);
+    if (spread > C::S) char_submit<C, DOX, DOY, false>(dm, 0, st, a);
 }
 
 template <class C, bool DOX, bool DOY>
 void char_all_launch(const Dims& dm, const typename C::T* v, const double* s, int spread,
                      typename C::T* dX, typename C::T* dY, hipStream_t st) {
     using T = typename C::T;
-    const T s2 = T(C::DIM == 3 ? s[2] : 0.0);
-    characteristics_all_kernel<C, DOX, DOY>
-        <<<tile_blocks<C>(dm), kThreads, C::DIM * tile_lds_bytes<C>(), st>>>(dm, v, T(s[0]), T(s[1]),
-                                                                          s2, dX, dY);
+    using B = CharacteristicsAllBody<C, DOX, DOY>;
+    const CharacteristicsAllArgs<T> a{dm, v, T(s[0]), T(s[1]), T(C::DIM == 3 ? s[2] : 0.0), dX, dY};
+    submit<B, TileFamily<C, B, CharacteristicsAllAnyBody<T, C::S, DOX, DOY>>>(
+        dim3(tile_blocks<C>(dm)), C::DIM * tile_lds_bytes<C>(), st, a);
     if (spread > C::S)
-        characteristics_kernel<C, DOX, DOY, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
-            dm, v, T(s[0]), T(s[1]), s2, dX, dY);
+        char_submit<C, DOX, DOY, false>(dm, 0, st,
+                                        CharacteristicsArgs<T>{dm, v, a.s0, a.s1, a.s2, dX, dY});
 }
 
 // LDS per workgroup on gfx950
@@ -841,12 +974,16 @@ void step_kernels(const Dims& dm, const typename C::T* src, const typename C::T*
                   const typename C::T* fac, double ht, double sgn, int spread,
                   typename C::T* out, int* table, int table_write, hipStream_t st) {
     using T = typename C::T;
-    sl_step_kernel<C, EPI, true><<<tile_blocks<C>(dm), kThreads, tile_lds_bytes<C>(), st>>>(
-        dm, src, disp, fac, T(ht), T(sgn), out, table, table_write);
+    using BL = SlStepBody<C, EPI, true>;
+    using BG = SlStepBody<C, EPI, false>;
+    submit<BL, TileFamily<C, BL, SlStepAnyBody<T, C::S, EPI, true>>>(
+        dim3(tile_blocks<C>(dm)), tile_lds_bytes<C>(), st,
+        SlStepArgs<T>{dm, src, disp, fac, T(ht), T(sgn), out, table, table_write});
     // the direct-gather kernel reads the table only once it is complete
     if (spread > C::S)
-        sl_step_kernel<C, EPI, false><<<tile_blocks<C>(dm), kThreads, 0, st>>>(
-            dm, src, disp, fac, T(ht), T(sgn), out, table, 0);
+        submit<BG, TileFamily<C, BG, SlStepAnyBody<T, C::S, EPI, false>>>(
+            dim3(tile_blocks<C>(dm)), 0, st,
+            SlStepArgs<T>{dm, src, disp, fac, T(ht), T(sgn), out, table, 0});
 }
 
 template <class C>
@@ -881,8 +1018,15 @@ void dispatch_tile(const Dims& dm, int spread, F&& f) {
         else if constexpr (sizeof(T) == 8) f(Tile<T, 3, 4>{});
         else f(Tile<T, 3, 8>{});
     } else {
-        if (pick_capacity<T, 2>(spread) == 8) f(Tile<T, 2, 8>{});
-        else f(Tile<T, 2, 16>{});
+        // the 2-D tile variant (points per thread) chosen for this grid size
+        auto cap = [&](auto p) {
+            constexpr int P = decltype(p)::value;
+            if (pick_capacity<T, 2>(spread) == 8) f(Tile<T, 2, 8, P>{});
+            else f(Tile<T, 2, 16, P>{});
+        };
+        if (dm.tile == 2) cap(std::integral_constant<int, 2>{});
+        else if (dm.tile == 4) cap(std::integral_constant<int, 4>{});
+        else cap(std::integral_constant<int, kTile2Default>{});
     }
 }
 
@@ -906,9 +1050,9 @@ hipError_t launch_velocity_max(const Dims& dm, const T* v, const double* s, doub
     const int nb = reduction_blocks(dm.N);
     constexpr int W = 16 / (int)sizeof(T);
     const int vec = (dm.N % W == 0 && (reinterpret_cast<unsigned long long>(v) & 15) == 0) ? 1 : 0;
-    velocity_max_kernel<T><<<nb, kThreads, 0, st>>>(v, dm.N, dm.dim, s[0], s[1],
-                                                    dm.dim == 3 ? s[2] : 0.0, vec, partial);
-    finish_kernel<true><<<finish_blocks(1), 1024, 0, st>>>(partial, nb, 1, res);
+    submit<VelocityMaxBody<T>>(dim3(nb), 0, st, VelocityMaxArgs<T>{v, dm.N, dm.dim, s[0], s[1],
+                                                    dm.dim == 3 ? s[2] : 0.0, vec, partial});
+    launch_finish<true>(partial, nb, 1, res, st);
     return hipGetLastError();
 }
 
@@ -950,9 +1094,12 @@ hipError_t launch_source_factor(const Dims& dm, const T* delta, const T* disp, d
 }
 
 // The tile geometry does not depend on the window capacity: one table serves
-// every variant.
+// every capacity.  In 2-D it is sized for the smallest tile variant (the most
+// tiles), so that any variant the autotuner picks fits.
 template <typename T>
-long long window_table_ints(const Dims& dm) {
+long long window_table_ints(const Dims& dm0) {
+    Dims dm = dm0;
+    if (dm.dim == 2) dm.tile = 2;
     long long n = 0;
     dispatch_tile<T>(dm, 0, [&](auto tile) {
         using C = decltype(tile);

@@ -18,6 +18,7 @@
 
 #include "fft_core.hpp"
 #include "launch.hpp"
+#include "group.hpp"
 #include "reduce.hpp"
 
 namespace gan {
@@ -106,6 +107,29 @@ void with_length(int L, F&& f) {
     }
 }
 
+// The same choice on the device, for the bodies of merged launches whose
+// classes have different lengths.  Only the compiled lengths merge (the
+// runtime-plan body keeps its arrays in scratch once inlined beside the
+// others), so the host submits other lengths as families of their own.
+template <typename F>
+__device__ __forceinline__ void with_length_dev(int L, F&& f) {
+    switch (L) {
+        case 32: f(std::integral_constant<int, 32>{}); break;
+        case 64: f(std::integral_constant<int, 64>{}); break;
+        case 96: f(std::integral_constant<int, 96>{}); break;
+        case 128: f(std::integral_constant<int, 128>{}); break;
+        case 192: f(std::integral_constant<int, 192>{}); break;
+        case 256: f(std::integral_constant<int, 256>{}); break;
+        case 384: f(std::integral_constant<int, 384>{}); break;
+        case 512: f(std::integral_constant<int, 512>{}); break;
+        default: break;
+    }
+}
+// The merged family of a length: its Any body for a compiled length, the
+// length's own body otherwise.
+template <int LC, class Body, class AnyBody>
+using MergeFamily = typename std::conditional<LC == 0, Body, AnyBody>::type;
+
 // Item e of a tile of NP real pencils x L: its pencil r and position i.
 // Strided axes put the pencil index fastest (coalesced over adjacent
 // pencils); the contiguous axis puts the position fastest.
@@ -119,7 +143,7 @@ __device__ inline void item_pos(int axis, int q, int L, int npshift, int& r, int
     }
 }
 
-template <typename T>
+template <typename T, int MT>
 struct DerivArgs {
     Dims dm;
     FftPlan<T> pl;
@@ -128,83 +152,91 @@ struct DerivArgs {
     int accumulate;
     int has_g;
     T* out;
-    const T* F[kMaxTime];
-    const T* G[kMaxTime];
-    double w[kMaxTime];
+    const T* F[MT];
+    const T* G[MT];
+    double w[MT];
 };
+// Launches with at most kGroupTime time levels carry the short argument list
+// (small enough to merge the launches of a group handle's classes).
+constexpr int kGroupTime = 9;
 
 // out = [out +] sum_t w_t G_t d/dx_axis F_t over one tile of 2 PC real pencils.
 // The loads of G_t and F_{t+1} are issued before the transforms of step t so
 // that they complete while the LDS passes run.
-template <typename T, int LC>
-__global__ void __launch_bounds__(kFftThreads) deriv_axis_kernel(DerivArgs<T> a) {
-    const int L = LC > 0 ? LC : a.pl.L;
-    const int PC = 1 << a.pcshift;
-    const int npshift = a.pcshift + 1;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + lpad_size(PC * L);
-    const FftPlan<T>& pl = a.pl;
-    const C2<T>* tw = twiddles_to_lds(a.pl, bufB + lpad_size(PC * L));
-    const Dims& dm = a.dm;
-    const long long npen = pencil_count(dm, a.axis, dm.n[2]);
-    const long long stride = pencil_stride(dm, a.axis, dm.n[2]);
-    const long long p0 = (long long)blockIdx.x << npshift;
-    const int nitems = (2 * PC) * L;
-    const T inv_l = T(1) / T(L);
+template <typename T, int LC, int MT>
+struct DerivAxisBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = DerivArgs<T, MT>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const DerivArgs<T, MT>& a = args_;
+        const int L = LC > 0 ? LC : a.pl.L;
+        const int PC = 1 << a.pcshift;
+        const int npshift = a.pcshift + 1;
+        C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+        C2<T>* bufB = bufA + lpad_size(PC * L);
+        const FftPlan<T>& pl = a.pl;
+        const C2<T>* tw = twiddles_to_lds(a.pl, bufB + lpad_size(PC * L));
+        const Dims& dm = a.dm;
+        const long long npen = pencil_count(dm, a.axis, dm.n[2]);
+        const long long stride = pencil_stride(dm, a.axis, dm.n[2]);
+        const long long p0 = (long long)bk.x << npshift;
+        const int nitems = (2 * PC) * L;
+        const T inv_l = T(1) / T(L);
 
-    long long off[kItems];
-    int slot[kItems];  // T index in bufA: 2 * complex index + (0 real | 1 imag); -1: no item
-    bool ok[kItems];
-    T acc[kItems], fv[kItems], gv[kItems];
-#pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        slot[e] = -1;
-        ok[e] = false;
-        off[e] = 0;
-        if (q < nitems) {
-            int r, i;
-            item_pos(a.axis, q, L, npshift, r, i);
-            slot[e] = 2 * lpad((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
-            ok[e] = p0 + r < npen;
-            if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
-        }
-        acc[e] = (ok[e] && a.accumulate) ? a.out[off[e]] : T(0);
-        fv[e] = ok[e] ? a.F[0][off[e]] : T(0);
-        gv[e] = T(1);
-    }
-    T* flat = reinterpret_cast<T*>(bufA);
-    for (int t = 0; t < a.ntime; ++t) {
-#pragma unroll
-        for (int e = 0; e < kItems; ++e)
-            if (slot[e] >= 0) flat[slot[e]] = fv[e];
-        __syncthreads();
-        const T* G = a.has_g ? a.G[t] : nullptr;
-        const bool more = t + 1 < a.ntime;
-        const T* Fn = more ? a.F[t + 1] : nullptr;
-#pragma unroll
+        long long off[kItems];
+        int slot[kItems];  // T index in bufA: 2 * complex index + (0 real | 1 imag); -1: no item
+        bool ok[kItems];
+        T acc[kItems], fv[kItems], gv[kItems];
+    #pragma unroll
         for (int e = 0; e < kItems; ++e) {
-            if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
-            if (more) fv[e] = ok[e] ? Fn[off[e]] : T(0);
+            const int q = threadIdx.x + e * kFftThreads;
+            slot[e] = -1;
+            ok[e] = false;
+            off[e] = 0;
+            if (q < nitems) {
+                int r, i;
+                item_pos(a.axis, q, L, npshift, r, i);
+                slot[e] = 2 * lpad((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
+                ok[e] = p0 + r < npen;
+                if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
+            }
+            acc[e] = (ok[e] && a.accumulate) ? a.out[off[e]] : T(0);
+            fv[e] = ok[e] ? a.F[0][off[e]] : T(0);
+            gv[e] = T(1);
         }
-        C2<T>* X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
-        for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
-            const int i = q >> a.pcshift;
-            X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
+        T* flat = reinterpret_cast<T*>(bufA);
+        for (int t = 0; t < a.ntime; ++t) {
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e)
+                if (slot[e] >= 0) flat[slot[e]] = fv[e];
+            __syncthreads();
+            const T* G = a.has_g ? a.G[t] : nullptr;
+            const bool more = t + 1 < a.ntime;
+            const T* Fn = more ? a.F[t + 1] : nullptr;
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
+                if (more) fv[e] = ok[e] ? Fn[off[e]] : T(0);
+            }
+            C2<T>* X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
+            for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
+                const int i = q >> a.pcshift;
+                X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
+            }
+            __syncthreads();
+            const C2<T>* Y = tile_fft<T, LC>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
+            const T* yflat = reinterpret_cast<const T*>(Y);
+            const T wt = T(a.w[t]);
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e)
+                if (ok[e]) acc[e] += wt * gv[e] * yflat[slot[e]];
+            __syncthreads();
         }
-        __syncthreads();
-        const C2<T>* Y = tile_fft<T, LC>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
-        const T* yflat = reinterpret_cast<const T*>(Y);
-        const T wt = T(a.w[t]);
-#pragma unroll
+    #pragma unroll
         for (int e = 0; e < kItems; ++e)
-            if (ok[e]) acc[e] += wt * gv[e] * yflat[slot[e]];
-        __syncthreads();
+            if (ok[e]) a.out[off[e]] = acc[e];
     }
-#pragma unroll
-    for (int e = 0; e < kItems; ++e)
-        if (ok[e]) a.out[off[e]] = acc[e];
-}
+};
 
 template <typename T>
 struct SpecPtrs {
@@ -222,147 +254,180 @@ struct OutPtrs {
 
 // Real rows (axis 2) of type TI -> half-spectrum rows computed and stored in
 // precision TC, for field blockIdx.y.
+template <typename TI, typename TC>
+struct R2cRowsArgs {
+    Dims dm;
+    FftPlan<TC> pl0;
+    int pcshift;
+    InPtrs<TI> ip;
+    SpecPtrs<TC> sp;
+};
 template <typename TI, typename TC, int LC>
-__global__ void __launch_bounds__(kFftThreads) r2c_rows_kernel(Dims dm, FftPlan<TC> pl0, int pcshift,
-                                                               InPtrs<TI> ip, SpecPtrs<TC> sp) {
-    using T = TC;
-    const int L = LC > 0 ? LC : pl0.L;
-    const int PC = 1 << pcshift;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + lpad_size(PC * L);
-    const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
-    const TI* in = ip.in[blockIdx.y];
-    C2<T>* spec = sp.spec[blockIdx.y];
-    const long long rows = (long long)dm.n[0] * dm.n[1];
-    const long long q0 = (long long)blockIdx.x * 2 * PC;
-    const int nitems = 2 * PC * L;
-    T* flat = reinterpret_cast<T*>(bufA);
-    // rows of a compiled length that is a multiple of 16 bytes move with
-    // 16-byte loads, WI consecutive elements per thread
-    constexpr int WI = 16 / (int)sizeof(TI);
-    if (LC > 0 && LC % WI == 0 && (reinterpret_cast<unsigned long long>(in) & 15) == 0) {
-        struct alignas(16) V {
-            TI x[WI];
-        };
-        V vals[kItems / WI];
-#pragma unroll
-        for (int e = 0; e < kItems / WI; ++e) {
-            const int q = (threadIdx.x + e * kFftThreads) * WI;
-            const int r = q / L, i = q - r * L;
-            if (q < nitems && q0 + r < rows) {
-                vals[e] = *reinterpret_cast<const V*>(in + (q0 + r) * L + i);
-            } else {
-#pragma unroll
-                for (int w = 0; w < WI; ++w) vals[e].x[w] = TI(0);
-            }
-        }
-#pragma unroll
-        for (int e = 0; e < kItems / WI; ++e) {
-            const int q = (threadIdx.x + e * kFftThreads) * WI;
-            if (q < nitems) {
+struct R2cRowsBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = R2cRowsArgs<TI, TC>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const FftPlan<TC>& pl0 = args_.pl0;
+        int pcshift = args_.pcshift;
+        const InPtrs<TI>& ip = args_.ip;
+        const SpecPtrs<TC>& sp = args_.sp;
+        using T = TC;
+        const int L = LC > 0 ? LC : pl0.L;
+        const int PC = 1 << pcshift;
+        C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+        C2<T>* bufB = bufA + lpad_size(PC * L);
+        const FftPlan<T>& pl = pl0;
+        const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+        const TI* in = ip.in[bk.y];
+        C2<T>* spec = sp.spec[bk.y];
+        const long long rows = (long long)dm.n[0] * dm.n[1];
+        const long long q0 = (long long)bk.x * 2 * PC;
+        const int nitems = 2 * PC * L;
+        T* flat = reinterpret_cast<T*>(bufA);
+        // rows of a compiled length that is a multiple of 16 bytes move with
+        // 16-byte loads, WI consecutive elements per thread
+        constexpr int WI = 16 / (int)sizeof(TI);
+        if (LC > 0 && LC % WI == 0 && (reinterpret_cast<unsigned long long>(in) & 15) == 0) {
+            struct alignas(16) V {
+                TI x[WI];
+            };
+            V vals[kItems / WI];
+    #pragma unroll
+            for (int e = 0; e < kItems / WI; ++e) {
+                const int q = (threadIdx.x + e * kFftThreads) * WI;
                 const int r = q / L, i = q - r * L;
-#pragma unroll
-                for (int w = 0; w < WI; ++w)
-                    flat[2 * lpad(((i + w) << pcshift) + (r & (PC - 1))) + (r >> pcshift)] =
-                        T(vals[e].x[w]);
+                if (q < nitems && q0 + r < rows) {
+                    vals[e] = *reinterpret_cast<const V*>(in + (q0 + r) * L + i);
+                } else {
+    #pragma unroll
+                    for (int w = 0; w < WI; ++w) vals[e].x[w] = TI(0);
+                }
             }
-        }
-    } else {
-        T vals[kItems];
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            const int r = q / L, i = q - r * L;
-            vals[e] = (q < nitems && q0 + r < rows) ? T(in[(q0 + r) * L + i]) : T(0);
-        }
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q < nitems) {
+    #pragma unroll
+            for (int e = 0; e < kItems / WI; ++e) {
+                const int q = (threadIdx.x + e * kFftThreads) * WI;
+                if (q < nitems) {
+                    const int r = q / L, i = q - r * L;
+    #pragma unroll
+                    for (int w = 0; w < WI; ++w)
+                        flat[2 * lpad(((i + w) << pcshift) + (r & (PC - 1))) + (r >> pcshift)] =
+                            T(vals[e].x[w]);
+                }
+            }
+        } else {
+            T vals[kItems];
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
                 const int r = q / L, i = q - r * L;
-                flat[2 * lpad((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+                vals[e] = (q < nitems && q0 + r < rows) ? T(in[(q0 + r) * L + i]) : T(0);
             }
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems) {
+                    const int r = q / L, i = q - r * L;
+                    flat[2 * lpad((i << pcshift) + (r & (PC - 1))) + (r >> pcshift)] = vals[e];
+                }
+            }
+        }
+        __syncthreads();
+        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
+        const int nh = dm.n2h;
+        for (int q = threadIdx.x; q < 2 * PC * nh; q += kFftThreads) {
+            const int r = q / nh, k = q - r * nh;
+            if (q0 + r >= rows) continue;
+            const int p = r & (PC - 1);
+            const C2<T> zk = Z[lpad((k << pcshift) + p)];
+            const int km = k == 0 ? 0 : L - k;
+            const C2<T> zm = Z[lpad((km << pcshift) + p)];
+            C2<T> o;
+            if ((r >> pcshift) == 0) o = cmk(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
+            else o = cmk(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
+            spec[(q0 + r) * nh + k] = o;
         }
     }
-    __syncthreads();
-    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
-    const int nh = dm.n2h;
-    for (int q = threadIdx.x; q < 2 * PC * nh; q += kFftThreads) {
-        const int r = q / nh, k = q - r * nh;
-        if (q0 + r >= rows) continue;
-        const int p = r & (PC - 1);
-        const C2<T> zk = Z[lpad((k << pcshift) + p)];
-        const int km = k == 0 ? 0 : L - k;
-        const C2<T> zm = Z[lpad((km << pcshift) + p)];
-        C2<T> o;
-        if ((r >> pcshift) == 0) o = cmk(T(0.5) * (zk.x + zm.x), T(0.5) * (zk.y - zm.y));
-        else o = cmk(T(0.5) * (zk.y + zm.y), T(0.5) * (zm.x - zk.x));
-        spec[(q0 + r) * nh + k] = o;
-    }
-}
+};
 
 // In-place complex transform of the half spectrum along axis 0 or 1, on tiles
 // of PC adjacent pencils.
+template <typename T>
+struct C2cAxisArgs {
+    Dims dm;
+    FftPlan<T> pl0;
+    int axis;
+    int pcshift;
+    int dir;
+    SpecPtrs<T> sp;
+};
 template <typename T, int LC>
-__global__ void __launch_bounds__(kFftThreads) c2c_axis_kernel(Dims dm, FftPlan<T> pl0, int axis,
-                                                               int pcshift, int dir,
-                                                               SpecPtrs<T> sp) {
-    const int L = LC > 0 ? LC : pl0.L;
-    const int PC = 1 << pcshift;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + lpad_size(PC * L);
-    const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
-    C2<T>* spec = sp.spec[blockIdx.y];
-    const int nh = dm.n2h;
-    const long long npen = pencil_count(dm, axis, nh);
-    const long long stride = pencil_stride(dm, axis, nh);
-    const long long ntiles = (npen + PC - 1) >> pcshift;
-    const int pl_ = threadIdx.x & (PC - 1);
-    const int nitems = PC * L;
-    // Tiles of PC adjacent pencils, grid-strided over the workgroups; the next
-    // tile's data is loaded into registers while the current one transforms.
-    auto load = [&](long long tile, C2<T>* vals, long long& base, bool& ok) {
-        const long long p = (tile << pcshift) + pl_;
-        ok = p < npen;
-        base = ok ? pencil_base(dm, axis, nh, p) : 0;
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            vals[e] = (q < nitems && ok) ? spec[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+struct C2cAxisBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2cAxisArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const FftPlan<T>& pl0 = args_.pl0;
+        int axis = args_.axis;
+        int pcshift = args_.pcshift;
+        int dir = args_.dir;
+        const SpecPtrs<T>& sp = args_.sp;
+        const int L = LC > 0 ? LC : pl0.L;
+        const int PC = 1 << pcshift;
+        C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+        C2<T>* bufB = bufA + lpad_size(PC * L);
+        const FftPlan<T>& pl = pl0;
+        const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+        C2<T>* spec = sp.spec[bk.y];
+        const int nh = dm.n2h;
+        const long long npen = pencil_count(dm, axis, nh);
+        const long long stride = pencil_stride(dm, axis, nh);
+        const long long ntiles = (npen + PC - 1) >> pcshift;
+        const int pl_ = threadIdx.x & (PC - 1);
+        const int nitems = PC * L;
+        // Tiles of PC adjacent pencils, grid-strided over the workgroups; the next
+        // tile's data is loaded into registers while the current one transforms.
+        auto load = [&](long long tile, C2<T>* vals, long long& base, bool& ok) {
+            const long long p = (tile << pcshift) + pl_;
+            ok = p < npen;
+            base = ok ? pencil_base(dm, axis, nh, p) : 0;
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                vals[e] = (q < nitems && ok) ? spec[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+            }
+        };
+        long long tile = bk.x;
+        if (tile >= ntiles) return;
+        C2<T> vals[kItems];
+        long long base;
+        bool ok;
+        load(tile, vals, base, ok);
+        for (;;) {
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems) bufA[lpad(q)] = vals[e];
+            }
+            __syncthreads();
+            const long long next = tile + bk.gx;
+            long long nbase = 0;
+            bool nok = false;
+            if (next < ntiles) load(next, vals, nbase, nok);
+            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
+    #pragma unroll
+            for (int e = 0; e < kItems; ++e) {
+                const int q = threadIdx.x + e * kFftThreads;
+                if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
+            }
+            if (next >= ntiles) break;
+            __syncthreads();  // every thread has read Z before bufA is refilled
+            tile = next;
+            base = nbase;
+            ok = nok;
         }
-    };
-    long long tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    C2<T> vals[kItems];
-    long long base;
-    bool ok;
-    load(tile, vals, base, ok);
-    for (;;) {
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q < nitems) bufA[lpad(q)] = vals[e];
-        }
-        __syncthreads();
-        const long long next = tile + gridDim.x;
-        long long nbase = 0;
-        bool nok = false;
-        if (next < ntiles) load(next, vals, nbase, nok);
-        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
-        }
-        if (next >= ntiles) break;
-        __syncthreads();  // every thread has read Z before bufA is refilled
-        tile = next;
-        base = nbase;
-        ok = nok;
     }
-}
+};
 
 // Workgroups for a grid-strided transform of `tiles` tiles per field: about
 // `per` tiles each, so that the prefetch of the next tile has a tile to
@@ -373,103 +438,120 @@ inline unsigned strided_blocks(long long tiles, int per) {
 }
 
 // Half-spectrum rows -> real rows: out = scale * x [+ add].
+template <typename T>
+struct C2rRowsArgs {
+    Dims dm;
+    FftPlan<T> pl0;
+    int pcshift;
+    T scale;
+    SpecPtrs<T> sp;
+    OutPtrs<T> op;
+};
 template <typename T, int LC>
-__global__ void __launch_bounds__(kFftThreads) c2r_rows_kernel(Dims dm, FftPlan<T> pl0, int pcshift,
-                                                               T scale, SpecPtrs<T> sp,
-                                                               OutPtrs<T> op) {
-    const int L = LC > 0 ? LC : pl0.L;
-    const int PC = 1 << pcshift;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + lpad_size(PC * L);
-    const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
-    const C2<T>* spec = sp.spec[blockIdx.y];
-    T* out = op.out[blockIdx.y];
-    const T* add = op.add[blockIdx.y];
-    const long long rows = (long long)dm.n[0] * dm.n[1];
-    const long long q0 = (long long)blockIdx.x * 2 * PC;
-    const int nh = dm.n2h;
-    const int nitems = PC * L;
-    constexpr int EH = kItems / 2;  // PC L <= kFftThreads * kItems / 2
-    C2<T> A[EH], B[EH];
-#pragma unroll
-    for (int e = 0; e < EH; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        const int p = q / L, i = q - p * L;
-        const int ks = 2 * i > L ? L - i : i;
-        A[e] = (q < nitems && q0 + p < rows) ? spec[(q0 + p) * nh + ks] : cmk(T(0), T(0));
-        B[e] = (q < nitems && q0 + p + PC < rows) ? spec[(q0 + p + PC) * nh + ks] : cmk(T(0), T(0));
-    }
-#pragma unroll
-    for (int e = 0; e < EH; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        if (q >= nitems) continue;
-        const int p = q / L, i = q - p * L;
-        const bool upper = 2 * i > L;
-        const int ks = upper ? L - i : i;
-        C2<T> a = A[e], b = B[e];
-        if (ks == 0 || 2 * ks == L) {
-            a.y = T(0);
-            b.y = T(0);
+struct C2rRowsBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2rRowsArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const FftPlan<T>& pl0 = args_.pl0;
+        int pcshift = args_.pcshift;
+        T scale = args_.scale;
+        const SpecPtrs<T>& sp = args_.sp;
+        const OutPtrs<T>& op = args_.op;
+        const int L = LC > 0 ? LC : pl0.L;
+        const int PC = 1 << pcshift;
+        C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+        C2<T>* bufB = bufA + lpad_size(PC * L);
+        const FftPlan<T>& pl = pl0;
+        const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+        const C2<T>* spec = sp.spec[bk.y];
+        T* out = op.out[bk.y];
+        const T* add = op.add[bk.y];
+        const long long rows = (long long)dm.n[0] * dm.n[1];
+        const long long q0 = (long long)bk.x * 2 * PC;
+        const int nh = dm.n2h;
+        const int nitems = PC * L;
+        constexpr int EH = kItems / 2;  // PC L <= kFftThreads * kItems / 2
+        C2<T> A[EH], B[EH];
+    #pragma unroll
+        for (int e = 0; e < EH; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            const int p = q / L, i = q - p * L;
+            const int ks = 2 * i > L ? L - i : i;
+            A[e] = (q < nitems && q0 + p < rows) ? spec[(q0 + p) * nh + ks] : cmk(T(0), T(0));
+            B[e] = (q < nitems && q0 + p + PC < rows) ? spec[(q0 + p + PC) * nh + ks] : cmk(T(0), T(0));
         }
-        if (upper) {
-            a.y = -a.y;
-            b.y = -b.y;
-        }
-        bufA[lpad((i << pcshift) + p)] = cmk(a.x - b.y, a.y + b.x);
-    }
-    __syncthreads();
-    const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
-    constexpr int W = 16 / (int)sizeof(T);
-    if (LC > 0 && LC % W == 0 && (reinterpret_cast<unsigned long long>(out) & 15) == 0 &&
-        (reinterpret_cast<unsigned long long>(add) & 15) == 0) {
-        // 16-byte stores (and loads of add), W consecutive elements per thread
-        struct alignas(16) V {
-            T x[W];
-        };
-        V addv[kItems / W];
-#pragma unroll
-        for (int e = 0; e < kItems / W; ++e) {
-            const int q = (threadIdx.x + e * kFftThreads) * W;
-            const int r = q / L, i = q - r * L;
-            if (add && q < 2 * nitems && q0 + r < rows) {
-                addv[e] = *reinterpret_cast<const V*>(add + (q0 + r) * L + i);
-            } else {
-#pragma unroll
-                for (int w = 0; w < W; ++w) addv[e].x[w] = T(0);
+    #pragma unroll
+        for (int e = 0; e < EH; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            if (q >= nitems) continue;
+            const int p = q / L, i = q - p * L;
+            const bool upper = 2 * i > L;
+            const int ks = upper ? L - i : i;
+            C2<T> a = A[e], b = B[e];
+            if (ks == 0 || 2 * ks == L) {
+                a.y = T(0);
+                b.y = T(0);
             }
+            if (upper) {
+                a.y = -a.y;
+                b.y = -b.y;
+            }
+            bufA[lpad((i << pcshift) + p)] = cmk(a.x - b.y, a.y + b.x);
         }
-#pragma unroll
-        for (int e = 0; e < kItems / W; ++e) {
-            const int q = (threadIdx.x + e * kFftThreads) * W;
+        __syncthreads();
+        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+        constexpr int W = 16 / (int)sizeof(T);
+        if (LC > 0 && LC % W == 0 && (reinterpret_cast<unsigned long long>(out) & 15) == 0 &&
+            (reinterpret_cast<unsigned long long>(add) & 15) == 0) {
+            // 16-byte stores (and loads of add), W consecutive elements per thread
+            struct alignas(16) V {
+                T x[W];
+            };
+            V addv[kItems / W];
+    #pragma unroll
+            for (int e = 0; e < kItems / W; ++e) {
+                const int q = (threadIdx.x + e * kFftThreads) * W;
+                const int r = q / L, i = q - r * L;
+                if (add && q < 2 * nitems && q0 + r < rows) {
+                    addv[e] = *reinterpret_cast<const V*>(add + (q0 + r) * L + i);
+                } else {
+    #pragma unroll
+                    for (int w = 0; w < W; ++w) addv[e].x[w] = T(0);
+                }
+            }
+    #pragma unroll
+            for (int e = 0; e < kItems / W; ++e) {
+                const int q = (threadIdx.x + e * kFftThreads) * W;
+                const int r = q / L, i = q - r * L;
+                if (q >= 2 * nitems || q0 + r >= rows) continue;
+                V o;
+    #pragma unroll
+                for (int w = 0; w < W; ++w) {
+                    const C2<T> z = Z[lpad(((i + w) << pcshift) + (r & (PC - 1)))];
+                    o.x[w] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e].x[w];
+                }
+                *reinterpret_cast<V*>(out + (q0 + r) * L + i) = o;
+            }
+            return;
+        }
+        T addv[kItems];
+    #pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
+            const int r = q / L, i = q - r * L;
+            addv[e] = (add && q < 2 * nitems && q0 + r < rows) ? add[(q0 + r) * L + i] : T(0);
+        }
+    #pragma unroll
+        for (int e = 0; e < kItems; ++e) {
+            const int q = threadIdx.x + e * kFftThreads;
             const int r = q / L, i = q - r * L;
             if (q >= 2 * nitems || q0 + r >= rows) continue;
-            V o;
-#pragma unroll
-            for (int w = 0; w < W; ++w) {
-                const C2<T> z = Z[lpad(((i + w) << pcshift) + (r & (PC - 1)))];
-                o.x[w] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e].x[w];
-            }
-            *reinterpret_cast<V*>(out + (q0 + r) * L + i) = o;
+            const C2<T> z = Z[lpad((i << pcshift) + (r & (PC - 1)))];
+            out[(q0 + r) * L + i] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e];
         }
-        return;
     }
-    T addv[kItems];
-#pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        const int r = q / L, i = q - r * L;
-        addv[e] = (add && q < 2 * nitems && q0 + r < rows) ? add[(q0 + r) * L + i] : T(0);
-    }
-#pragma unroll
-    for (int e = 0; e < kItems; ++e) {
-        const int q = threadIdx.x + e * kFftThreads;
-        const int r = q / L, i = q - r * L;
-        if (q >= 2 * nitems || q0 + r >= rows) continue;
-        const C2<T> z = Z[lpad((i << pcshift) + (r & (PC - 1)))];
-        out[(q0 + r) * L + i] = scale * ((r >> pcshift) ? z.y : z.x) + addv[e];
-    }
-}
+};
 
 // ---- pointwise operators on the half spectrum --------------------------------
 struct KVec {
@@ -535,47 +617,81 @@ __device__ inline void leray_point(const KVec& kv, int dim, C2<T>* u) {
 // |k|^(2p), so rounding noise of an FP32 transform in the high modes would be
 // amplified into the gradient.
 template <typename T>
-__global__ void spec_gradient_kernel(Dims dm, SpecOpParams sp, SpecPtrs<double> vh, SpecPtrs<T> bh,
-                                     SpecPtrs<T> gh) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const KVec kv = kvec(dm, lin);
-        const double al = seg_alpha(sp, dm, lin) * ipow(kv.k2, sp.p);
-        C2<T> b[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) b[c] = c < sp.dim ? bh.spec[c][lin] : cmk(T(0), T(0));
-        if (sp.leray) leray_point(kv, sp.dim, b);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (c < sp.dim) {
-                const C2<double> z = vh.spec[c][lin];
-                gh.spec[c][lin] = cmk(T(al * z.x + double(b[c].x)), T(al * z.y + double(b[c].y)));
-            }
+struct SpecGradientArgs {
+    Dims dm;
+    SpecOpParams sp;
+    SpecPtrs<double> vh;
+    SpecPtrs<T> bh;
+    SpecPtrs<T> gh;
+};
+template <typename T>
+struct SpecGradientBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecGradientArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const SpecOpParams& sp = args_.sp;
+        const SpecPtrs<double>& vh = args_.vh;
+        const SpecPtrs<T>& bh = args_.bh;
+        const SpecPtrs<T>& gh = args_.gh;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const KVec kv = kvec(dm, lin);
+            const double al = seg_alpha(sp, dm, lin) * ipow(kv.k2, sp.p);
+            C2<T> b[3];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) b[c] = c < sp.dim ? bh.spec[c][lin] : cmk(T(0), T(0));
+            if (sp.leray) leray_point(kv, sp.dim, b);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c < sp.dim) {
+                    const C2<double> z = vh.spec[c][lin];
+                    gh.spec[c][lin] = cmk(T(al * z.x + double(b[c].x)), T(al * z.y + double(b[c].y)));
+                }
+        }
     }
-}
+};
 
 template <typename T>
-__global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, SpecPtrs<T> sh,
-                                    SpecPtrs<T> keep, int has_keep) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const KVec kv = kvec(dm, lin);
-        double l = ipow(kv.k2, sp.p);
-        if (l == 0.0) l = 1.0;
-        const T f = T(-1.0 / (seg_alpha(sp, dm, lin) * l));
-        C2<T> g[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
-        if (sp.leray) leray_point(kv, sp.dim, g);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (c < sp.dim) {
-                const C2<T> z = cscale(g[c], f);
-                sh.spec[c][lin] = z;
-                if (has_keep) keep.spec[c][lin] = z;
-            }
+struct SpecPrecondArgs {
+    Dims dm;
+    SpecOpParams sp;
+    SpecPtrs<T> gh;
+    SpecPtrs<T> sh;
+    SpecPtrs<T> keep;
+    int has_keep;
+};
+template <typename T>
+struct SpecPrecondBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecPrecondArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const SpecOpParams& sp = args_.sp;
+        const SpecPtrs<T>& gh = args_.gh;
+        const SpecPtrs<T>& sh = args_.sh;
+        const SpecPtrs<T>& keep = args_.keep;
+        int has_keep = args_.has_keep;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const KVec kv = kvec(dm, lin);
+            double l = ipow(kv.k2, sp.p);
+            if (l == 0.0) l = 1.0;
+            const T f = T(-1.0 / (seg_alpha(sp, dm, lin) * l));
+            C2<T> g[3];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
+            if (sp.leray) leray_point(kv, sp.dim, g);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c < sp.dim) {
+                    const C2<T> z = cscale(g[c], f);
+                    sh.spec[c][lin] = z;
+                    if (has_keep) keep.spec[c][lin] = z;
+                }
+        }
     }
-}
+};
 
 // The last forward and the first inverse pass of the complex transforms along
 // `axis`, with a spectral operator in between, on tiles of PC pencils holding
@@ -586,98 +702,163 @@ __global__ void spec_precond_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, Sp
 // c2c_axis_kernel and spec_gradient_kernel / spec_precond_kernel, so the
 // result is bitwise that of the three separate passes, without the two
 // round trips of the spectra through HBM between them.
+template <typename T>
+struct C2cSpecArgs {
+    Dims dm;
+    FftPlan<T> pl0;
+    int axis;
+    int pcshift;
+    SpecOpParams sop;
+    SpecPtrs<T> io;
+    SpecPtrs<double> vh;
+    SpecPtrs<T> keep;
+    int has_keep;
+};
 template <typename T, int LC, int OP>
-__global__ void __launch_bounds__(kFftThreads) c2c_spec_kernel(Dims dm, FftPlan<T> pl0, int axis,
-                                                               int pcshift, SpecOpParams sop,
-                                                               SpecPtrs<T> io, SpecPtrs<double> vh,
-                                                               SpecPtrs<T> keep, int has_keep) {
-    const int L = LC > 0 ? LC : pl0.L;
-    const int PC = 1 << pcshift;
-    C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
-    C2<T>* bufB = bufA + lpad_size(PC * L);
-    const FftPlan<T>& pl = pl0;
-    const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
-    const int nh = dm.n2h;
-    const long long npen = pencil_count(dm, axis, nh);
-    const long long stride = pencil_stride(dm, axis, nh);
-    const long long ntiles = (npen + PC - 1) >> pcshift;
-    const int pl_ = threadIdx.x & (PC - 1);
-    const int nitems = PC * L;
-    const int dim = sop.dim;
-    for (long long tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const long long p = (tile << pcshift) + pl_;
-        const bool ok = p < npen;
-        const long long base = ok ? pencil_base(dm, axis, nh, p) : 0;
-        C2<T> R[3][kItems];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) break;
-            const C2<T>* src = io.spec[c];
-#pragma unroll
+struct C2cSpecBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2cSpecArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const FftPlan<T>& pl0 = args_.pl0;
+        int axis = args_.axis;
+        int pcshift = args_.pcshift;
+        const SpecOpParams& sop = args_.sop;
+        const SpecPtrs<T>& io = args_.io;
+        const SpecPtrs<double>& vh = args_.vh;
+        const SpecPtrs<T>& keep = args_.keep;
+        int has_keep = args_.has_keep;
+        const int L = LC > 0 ? LC : pl0.L;
+        const int PC = 1 << pcshift;
+        C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
+        C2<T>* bufB = bufA + lpad_size(PC * L);
+        const FftPlan<T>& pl = pl0;
+        const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+        const int nh = dm.n2h;
+        const long long npen = pencil_count(dm, axis, nh);
+        const long long stride = pencil_stride(dm, axis, nh);
+        const long long ntiles = (npen + PC - 1) >> pcshift;
+        const int pl_ = threadIdx.x & (PC - 1);
+        const int nitems = PC * L;
+        const int dim = sop.dim;
+        for (long long tile = bk.x; tile < ntiles; tile += bk.gx) {
+            const long long p = (tile << pcshift) + pl_;
+            const bool ok = p < npen;
+            const long long base = ok ? pencil_base(dm, axis, nh, p) : 0;
+            C2<T> R[3][kItems];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= dim) break;
+                const C2<T>* src = io.spec[c];
+    #pragma unroll
+                for (int e = 0; e < kItems; ++e) {
+                    const int q = threadIdx.x + e * kFftThreads;
+                    if (q < nitems)
+                        bufA[lpad(q)] = ok ? src[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+                }
+                __syncthreads();
+                const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
+    #pragma unroll
+                for (int e = 0; e < kItems; ++e) {
+                    const int q = threadIdx.x + e * kFftThreads;
+                    R[c][e] = q < nitems ? Z[lpad(q)] : cmk(T(0), T(0));
+                }
+                __syncthreads();
+            }
+    #pragma unroll
             for (int e = 0; e < kItems; ++e) {
                 const int q = threadIdx.x + e * kFftThreads;
-                if (q < nitems)
-                    bufA[lpad(q)] = ok ? src[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
+                if (q >= nitems || !ok) continue;
+                const long long lin = base + (q >> pcshift) * stride;
+                const KVec kv = kvec(dm, lin);
+                C2<T> g[3];
+    #pragma unroll
+                for (int c = 0; c < 3; ++c) g[c] = c < dim ? R[c][e] : cmk(T(0), T(0));
+                if (sop.leray) leray_point(kv, dim, g);
+                if constexpr (OP == kSpecGrad) {
+                    const double al = seg_alpha(sop, dm, lin) * ipow(kv.k2, sop.p);
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (c < dim) {
+                            const C2<double> z = vh.spec[c][lin];
+                            R[c][e] = cmk(T(al * z.x + double(g[c].x)), T(al * z.y + double(g[c].y)));
+                        }
+                } else {
+                    double l = ipow(kv.k2, sop.p);
+                    if (l == 0.0) l = 1.0;
+                    const T f = T(-1.0 / (seg_alpha(sop, dm, lin) * l));
+    #pragma unroll
+                    for (int c = 0; c < 3; ++c)
+                        if (c < dim) {
+                            R[c][e] = cscale(g[c], f);
+                            if (has_keep) keep.spec[c][lin] = R[c][e];
+                        }
+                }
             }
-            __syncthreads();
-            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
-#pragma unroll
-            for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
-                R[c][e] = q < nitems ? Z[lpad(q)] : cmk(T(0), T(0));
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= dim) break;
+    #pragma unroll
+                for (int e = 0; e < kItems; ++e) {
+                    const int q = threadIdx.x + e * kFftThreads;
+                    if (q < nitems) bufA[lpad(q)] = R[c][e];
+                }
+                __syncthreads();
+                const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+                C2<T>* dst = io.spec[c];
+    #pragma unroll
+                for (int e = 0; e < kItems; ++e) {
+                    const int q = threadIdx.x + e * kFftThreads;
+                    if (q < nitems && ok) dst[base + (q >> pcshift) * stride] = Z[lpad(q)];
+                }
+                __syncthreads();
             }
-            __syncthreads();
-        }
-#pragma unroll
-        for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
-            if (q >= nitems || !ok) continue;
-            const long long lin = base + (q >> pcshift) * stride;
-            const KVec kv = kvec(dm, lin);
-            C2<T> g[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) g[c] = c < dim ? R[c][e] : cmk(T(0), T(0));
-            if (sop.leray) leray_point(kv, dim, g);
-            if constexpr (OP == kSpecGrad) {
-                const double al = seg_alpha(sop, dm, lin) * ipow(kv.k2, sop.p);
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (c < dim) {
-                        const C2<double> z = vh.spec[c][lin];
-                        R[c][e] = cmk(T(al * z.x + double(g[c].x)), T(al * z.y + double(g[c].y)));
-                    }
-            } else {
-                double l = ipow(kv.k2, sop.p);
-                if (l == 0.0) l = 1.0;
-                const T f = T(-1.0 / (seg_alpha(sop, dm, lin) * l));
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-                    if (c < dim) {
-                        R[c][e] = cscale(g[c], f);
-                        if (has_keep) keep.spec[c][lin] = R[c][e];
-                    }
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) break;
-#pragma unroll
-            for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
-                if (q < nitems) bufA[lpad(q)] = R[c][e];
-            }
-            __syncthreads();
-            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
-            C2<T>* dst = io.spec[c];
-#pragma unroll
-            for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
-                if (q < nitems && ok) dst[base + (q >> pcshift) * stride] = Z[lpad(q)];
-            }
-            __syncthreads();
         }
     }
-}
+};
+
+// Bodies of merged launches: the transform length of each class is read from
+// its plan and dispatched to the body compiled for it.
+template <typename T, int MT>
+struct DerivAxisAnyBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = DerivArgs<T, MT>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_length_dev(a.pl.L, [&](auto lc) __attribute__((always_inline)) { DerivAxisBody<T, decltype(lc)::value, MT>::run(a, bk); });
+    }
+};
+template <typename TI, typename TC>
+struct R2cRowsAnyBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = R2cRowsArgs<TI, TC>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { R2cRowsBody<TI, TC, decltype(lc)::value>::run(a, bk); });
+    }
+};
+template <typename T>
+struct C2cAxisAnyBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2cAxisArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { C2cAxisBody<T, decltype(lc)::value>::run(a, bk); });
+    }
+};
+template <typename T>
+struct C2rRowsAnyBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2rRowsArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { C2rRowsBody<T, decltype(lc)::value>::run(a, bk); });
+    }
+};
+template <typename T, int OP>
+struct C2cSpecAnyBody {
+    static constexpr int kBlock = kFftThreads;
+    using Args = C2cSpecArgs<T>;
+    __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
+        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { C2cSpecBody<T, decltype(lc)::value, OP>::run(a, bk); });
+    }
+};
 
 // The coarse space of the two-level preconditioner on a grid of c_i cells per
 // axis: the wavenumbers |k_i| <= c_i/2 - 1 (the Nyquist modes, and for an odd
@@ -688,152 +869,254 @@ __device__ inline bool coarse_kept(int k, int c) { return 2 * (k < 0 ? -k : k) <
 // sh[c] = sign (alpha lbar_p)^expo P gh[c]; with band_cut the modes outside
 // the coarse space of this grid are set to zero.
 template <typename T>
-__global__ void spec_pow_kernel(Dims dm, SpecOpParams sp, SpecPtrs<T> gh, SpecPtrs<T> sh,
-                                double expo, double sign, int band_cut) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const int i2 = (int)(lin % dm.n2h);
-        const long long rest = lin / dm.n2h;
-        const int i1 = (int)(rest % dm.n[1]), i0 = (int)(rest / dm.n[1]);
-        const int k0 = dm.dim == 3 ? wavenumber(i0, dm.n[0]) : 0;
-        const bool kept = (dm.dim == 2 || coarse_kept(k0, dm.n[0])) &&
-                          coarse_kept(wavenumber(i1, dm.n[1]), dm.n[1]) && coarse_kept(i2, dm.n[2]);
-        const KVec kv = kvec(dm, lin);
-        double l = ipow(kv.k2, sp.p);
-        if (l == 0.0) l = 1.0;
-        const T f = (band_cut && !kept) ? T(0) : T(sign * pow(seg_alpha(sp, dm, lin) * l, expo));
-        C2<T> g[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
-        if (sp.leray) leray_point(kv, sp.dim, g);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-            if (c < sp.dim) sh.spec[c][lin] = cscale(g[c], f);
+struct SpecPowArgs {
+    Dims dm;
+    SpecOpParams sp;
+    SpecPtrs<T> gh;
+    SpecPtrs<T> sh;
+    double expo;
+    double sign;
+    int band_cut;
+};
+template <typename T>
+struct SpecPowBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecPowArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const SpecOpParams& sp = args_.sp;
+        const SpecPtrs<T>& gh = args_.gh;
+        const SpecPtrs<T>& sh = args_.sh;
+        double expo = args_.expo;
+        double sign = args_.sign;
+        int band_cut = args_.band_cut;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const int i2 = (int)(lin % dm.n2h);
+            const long long rest = lin / dm.n2h;
+            const int i1 = (int)(rest % dm.n[1]), i0 = (int)(rest / dm.n[1]);
+            const int k0 = dm.dim == 3 ? wavenumber(i0, dm.n[0]) : 0;
+            const bool kept = (dm.dim == 2 || coarse_kept(k0, dm.n[0])) &&
+                              coarse_kept(wavenumber(i1, dm.n[1]), dm.n[1]) && coarse_kept(i2, dm.n[2]);
+            const KVec kv = kvec(dm, lin);
+            double l = ipow(kv.k2, sp.p);
+            if (l == 0.0) l = 1.0;
+            const T f = (band_cut && !kept) ? T(0) : T(sign * pow(seg_alpha(sp, dm, lin) * l, expo));
+            C2<T> g[3];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) g[c] = c < sp.dim ? gh.spec[c][lin] : cmk(T(0), T(0));
+            if (sp.leray) leray_point(kv, sp.dim, g);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c)
+                if (c < sp.dim) sh.spec[c][lin] = cscale(g[c], f);
+        }
     }
-}
+};
 
 // Half spectra between a grid and the grid with half the cells per axis,
 // on the coarse space; every other entry of the destination is zero.
 // restrict: coarse(k) = scale fine(k);  prolong: fine(k) = scale coarse(k).
 
 template <typename T>
-__global__ void spec_restrict_kernel(Dims df, Dims dc, SpecPtrs<T> fine, SpecPtrs<T> coarse,
-                                     int count, T scale) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dc.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const int i2 = (int)(lin % dc.n2h);
-        const long long rest = lin / dc.n2h;
-        const int i1 = (int)(rest % dc.n[1]), i0 = (int)(rest / dc.n[1]);
-        const int k0 = dc.dim == 3 ? wavenumber(i0, dc.n[0]) : 0;
-        const int k1 = wavenumber(i1, dc.n[1]);
-        const bool keep = (dc.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
-                          coarse_kept(i2, dc.n[2]);
-        long long src = 0;
-        if (keep) {
-            const int f0 = dc.dim == 3 ? (k0 < 0 ? k0 + df.n[0] : k0) : i0;
-            const int f1 = k1 < 0 ? k1 + df.n[1] : k1;
-            src = ((long long)f0 * df.n[1] + f1) * df.n2h + i2;
+struct SpecRestrictArgs {
+    Dims df;
+    Dims dc;
+    SpecPtrs<T> fine;
+    SpecPtrs<T> coarse;
+    int count;
+    T scale;
+};
+template <typename T>
+struct SpecRestrictBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecRestrictArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& df = args_.df;
+        const Dims& dc = args_.dc;
+        const SpecPtrs<T>& fine = args_.fine;
+        const SpecPtrs<T>& coarse = args_.coarse;
+        int count = args_.count;
+        T scale = args_.scale;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < dc.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const int i2 = (int)(lin % dc.n2h);
+            const long long rest = lin / dc.n2h;
+            const int i1 = (int)(rest % dc.n[1]), i0 = (int)(rest / dc.n[1]);
+            const int k0 = dc.dim == 3 ? wavenumber(i0, dc.n[0]) : 0;
+            const int k1 = wavenumber(i1, dc.n[1]);
+            const bool keep = (dc.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
+                              coarse_kept(i2, dc.n[2]);
+            long long src = 0;
+            if (keep) {
+                const int f0 = dc.dim == 3 ? (k0 < 0 ? k0 + df.n[0] : k0) : i0;
+                const int f1 = k1 < 0 ? k1 + df.n[1] : k1;
+                src = ((long long)f0 * df.n[1] + f1) * df.n2h + i2;
+            }
+            for (int c = 0; c < count; ++c)
+                coarse.spec[c][lin] = keep ? cscale(fine.spec[c][src], scale) : cmk(T(0), T(0));
         }
-        for (int c = 0; c < count; ++c)
-            coarse.spec[c][lin] = keep ? cscale(fine.spec[c][src], scale) : cmk(T(0), T(0));
     }
-}
+};
 
 template <typename T>
-__global__ void spec_prolong_kernel(Dims df, Dims dc, SpecPtrs<T> coarse, SpecPtrs<T> fine,
-                                    int count, T scale) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < df.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const int i2 = (int)(lin % df.n2h);
-        const long long rest = lin / df.n2h;
-        const int i1 = (int)(rest % df.n[1]), i0 = (int)(rest / df.n[1]);
-        const int k0 = df.dim == 3 ? wavenumber(i0, df.n[0]) : 0;
-        const int k1 = wavenumber(i1, df.n[1]);
-        const bool keep = (df.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
-                          coarse_kept(i2, dc.n[2]);
-        long long src = 0;
-        if (keep) {
-            const int c0 = df.dim == 3 ? (k0 < 0 ? k0 + dc.n[0] : k0) : i0;
-            const int c1 = k1 < 0 ? k1 + dc.n[1] : k1;
-            src = ((long long)c0 * dc.n[1] + c1) * dc.n2h + i2;
+struct SpecProlongArgs {
+    Dims df;
+    Dims dc;
+    SpecPtrs<T> coarse;
+    SpecPtrs<T> fine;
+    int count;
+    T scale;
+};
+template <typename T>
+struct SpecProlongBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecProlongArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& df = args_.df;
+        const Dims& dc = args_.dc;
+        const SpecPtrs<T>& coarse = args_.coarse;
+        const SpecPtrs<T>& fine = args_.fine;
+        int count = args_.count;
+        T scale = args_.scale;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < df.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const int i2 = (int)(lin % df.n2h);
+            const long long rest = lin / df.n2h;
+            const int i1 = (int)(rest % df.n[1]), i0 = (int)(rest / df.n[1]);
+            const int k0 = df.dim == 3 ? wavenumber(i0, df.n[0]) : 0;
+            const int k1 = wavenumber(i1, df.n[1]);
+            const bool keep = (df.dim == 2 || coarse_kept(k0, dc.n[0])) && coarse_kept(k1, dc.n[1]) &&
+                              coarse_kept(i2, dc.n[2]);
+            long long src = 0;
+            if (keep) {
+                const int c0 = df.dim == 3 ? (k0 < 0 ? k0 + dc.n[0] : k0) : i0;
+                const int c1 = k1 < 0 ? k1 + dc.n[1] : k1;
+                src = ((long long)c0 * dc.n[1] + c1) * dc.n2h + i2;
+            }
+            for (int c = 0; c < count; ++c)
+                fine.spec[c][lin] = keep ? cscale(coarse.spec[c][src], scale) : cmk(T(0), T(0));
         }
-        for (int c = 0; c < count; ++c)
-            fine.spec[c][lin] = keep ? cscale(coarse.spec[c][src], scale) : cmk(T(0), T(0));
     }
-}
+};
 
 // Cross terms of the regulariser along a line: with the half-spectrum
 // weights (1 at k2 = 0 and at the Nyquist index, else 2),
 //   res[0] = sum w l_p Re(vh conj(sh)),  res[1] = sum w l_p |sh|^2.
 template <typename T>
-__global__ void __launch_bounds__(256) spec_cross_kernel(Dims dm, SpecOpParams sp,
-                                                         SpecPtrs<double> vh, SpecPtrs<T> sh,
-                                                         double* partial) {
-    __shared__ double red[256 / 64];
-    double a = 0.0, b = 0.0;
-    const long long len = dm.NH / gridDim.y, lo = blockIdx.y * len;
-    for (long long lin = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const KVec kv = kvec(dm, lin);
-        const int i2 = (int)(lin % dm.n2h);
-        const double wl = ((i2 == 0 || 2 * i2 == dm.n[2]) ? 1.0 : 2.0) * ipow(kv.k2, sp.p);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c >= sp.dim) continue;
-            const C2<double> z = vh.spec[c][lin];
-            const C2<T> q = sh.spec[c][lin];
-            a += wl * (z.x * double(q.x) + z.y * double(q.y));
-            b += wl * (double(q.x) * double(q.x) + double(q.y) * double(q.y));
+struct SpecCrossArgs {
+    Dims dm;
+    SpecOpParams sp;
+    SpecPtrs<double> vh;
+    SpecPtrs<T> sh;
+    double* partial;
+};
+template <typename T>
+struct SpecCrossBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecCrossArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const SpecOpParams& sp = args_.sp;
+        const SpecPtrs<double>& vh = args_.vh;
+        const SpecPtrs<T>& sh = args_.sh;
+        double* partial = args_.partial;
+        __shared__ double red[256 / 64];
+        double a = 0.0, b = 0.0;
+        const long long len = dm.NH / bk.gy, lo = bk.y * len;
+        for (long long lin = lo + bk.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
+             lin += (long long)bk.gx * blockDim.x) {
+            const KVec kv = kvec(dm, lin);
+            const int i2 = (int)(lin % dm.n2h);
+            const double wl = ((i2 == 0 || 2 * i2 == dm.n[2]) ? 1.0 : 2.0) * ipow(kv.k2, sp.p);
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= sp.dim) continue;
+                const C2<double> z = vh.spec[c][lin];
+                const C2<T> q = sh.spec[c][lin];
+                a += wl * (z.x * double(q.x) + z.y * double(q.y));
+                b += wl * (double(q.x) * double(q.x) + double(q.y) * double(q.y));
+            }
+        }
+        const double ra = block_reduce<false>(a, red);
+        const double rb = block_reduce<false>(b, red);
+        if (threadIdx.x == 0) {
+            partial[(long long)bk.y * bk.gx + bk.x] = ra;
+            partial[(long long)(bk.gy + bk.y) * bk.gx + bk.x] = rb;
         }
     }
-    const double ra = block_reduce<false>(a, red);
-    const double rb = block_reduce<false>(b, red);
-    if (threadIdx.x == 0) {
-        partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = ra;
-        partial[(long long)(gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = rb;
-    }
-}
+};
 
 // vh[c] += rho * sh[c]  (FP64 spectrum of v updated along a line)
 template <typename T>
-__global__ void spec_axpy_kernel(Dims dm, int dim, SpecPtrs<double> vh, SegCoef rc, SpecPtrs<T> sh) {
-    for (long long lin = blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const double rho = rc.c[spec_seg(dm, lin)];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            if (c >= dim) continue;
-            C2<double> z = vh.spec[c][lin];
-            const C2<T> q = sh.spec[c][lin];
-            z.x += rho * double(q.x);
-            z.y += rho * double(q.y);
-            vh.spec[c][lin] = z;
+struct SpecAxpyArgs {
+    Dims dm;
+    int dim;
+    SpecPtrs<double> vh;
+    SegCoef rc;
+    SpecPtrs<T> sh;
+};
+template <typename T>
+struct SpecAxpyBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecAxpyArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        int dim = args_.dim;
+        const SpecPtrs<double>& vh = args_.vh;
+        const SegCoef& rc = args_.rc;
+        const SpecPtrs<T>& sh = args_.sh;
+        for (long long lin = bk.x * (long long)blockDim.x + threadIdx.x; lin < dm.NH;
+             lin += (long long)bk.gx * blockDim.x) {
+            const double rho = rc.c[spec_seg(dm, lin)];
+    #pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (c >= dim) continue;
+                C2<double> z = vh.spec[c][lin];
+                const C2<T> q = sh.spec[c][lin];
+                z.x += rho * double(q.x);
+                z.y += rho * double(q.y);
+                vh.spec[c][lin] = z;
+            }
         }
     }
-}
+};
 
 template <typename T>
-__global__ void __launch_bounds__(256) spec_regvalue_kernel(Dims dm, SpecOpParams sp,
-                                                            SpecPtrs<T> vh, double* partial) {
-    __shared__ double sh[256 / 64];
-    double acc = 0.0;
-    const long long len = dm.NH / gridDim.y, lo = blockIdx.y * len;
-    for (long long lin = lo + blockIdx.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
-         lin += (long long)gridDim.x * blockDim.x) {
-        const KVec kv = kvec(dm, lin);
-        const int i2 = (int)(lin % dm.n2h);
-        const double wgt = (i2 == 0 || 2 * i2 == dm.n[2]) ? 1.0 : 2.0;
-        const double l = ipow(kv.k2, sp.p);
-        double s = 0.0;
-        for (int c = 0; c < sp.dim; ++c) {
-            const C2<T> z = vh.spec[c][lin];
-            s += double(z.x) * double(z.x) + double(z.y) * double(z.y);
+struct SpecRegvalueArgs {
+    Dims dm;
+    SpecOpParams sp;
+    SpecPtrs<T> vh;
+    double* partial;
+};
+template <typename T>
+struct SpecRegvalueBody {
+    static constexpr int kBlock = 256;
+    using Args = SpecRegvalueArgs<T>;
+    __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
+        const Dims& dm = args_.dm;
+        const SpecOpParams& sp = args_.sp;
+        const SpecPtrs<T>& vh = args_.vh;
+        double* partial = args_.partial;
+        __shared__ double sh[256 / 64];
+        double acc = 0.0;
+        const long long len = dm.NH / bk.gy, lo = bk.y * len;
+        for (long long lin = lo + bk.x * (long long)blockDim.x + threadIdx.x; lin < lo + len;
+             lin += (long long)bk.gx * blockDim.x) {
+            const KVec kv = kvec(dm, lin);
+            const int i2 = (int)(lin % dm.n2h);
+            const double wgt = (i2 == 0 || 2 * i2 == dm.n[2]) ? 1.0 : 2.0;
+            const double l = ipow(kv.k2, sp.p);
+            double s = 0.0;
+            for (int c = 0; c < sp.dim; ++c) {
+                const C2<T> z = vh.spec[c][lin];
+                s += double(z.x) * double(z.x) + double(z.y) * double(z.y);
+            }
+            acc += wgt * l * s;
         }
-        acc += wgt * l * s;
+        const double r = block_reduce<false>(acc, sh);
+        if (threadIdx.x == 0) partial[(long long)bk.y * bk.gx + bk.x] = r;
     }
-    const double r = block_reduce<false>(acc, sh);
-    if (threadIdx.x == 0) partial[(long long)blockIdx.y * gridDim.x + blockIdx.x] = r;
-}
+};
 
 // blocks per stacked problem of a spectral reduction of nq quantities
 inline int spec_red_blocks(const Dims& dm, int nq) {
@@ -856,28 +1139,42 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
                              const T* const* F, const T* const* G, const double* w, int ntime,
                              int accumulate, T* out, hipStream_t st) {
     if (ntime < 1 || ntime > kMaxTime) return hipErrorInvalidValue;
-    DerivArgs<T> a;
-    a.dm = dm;
-    a.pl = pl.p[axis];
-    a.axis = axis;
+    auto fill = [&](auto& a, int mt) {
+        a.dm = dm;
+        a.pl = pl.p[axis];
+        a.axis = axis;
+        a.pcshift = pc_shift_real(dm.n[axis], (int)sizeof(C2<T>), pencil_count(dm, axis, dm.n[2]));
+        a.ntime = ntime;
+        a.accumulate = accumulate;
+        a.has_g = G != nullptr;
+        a.out = out;
+        for (int t = 0; t < mt; ++t) {
+            a.F[t] = t < ntime ? F[t] : nullptr;
+            a.G[t] = (G && t < ntime) ? G[t] : nullptr;
+            a.w[t] = t < ntime ? w[t] : 0.0;
+        }
+    };
     const int L = dm.n[axis];
     const long long npen = pencil_count(dm, axis, dm.n[2]);
-    a.pcshift = pc_shift_real(L, (int)sizeof(C2<T>), npen);
-    a.ntime = ntime;
-    a.accumulate = accumulate;
-    a.has_g = G != nullptr;
-    a.out = out;
-    for (int t = 0; t < kMaxTime; ++t) {
-        a.F[t] = t < ntime ? F[t] : nullptr;
-        a.G[t] = (G && t < ntime) ? G[t] : nullptr;
-        a.w[t] = t < ntime ? w[t] : 0.0;
-    }
-    const int PC = 1 << a.pcshift;
+    const int PC = 1 << pc_shift_real(L, (int)sizeof(C2<T>), npen);
     const long long tiles = (npen + 2 * PC - 1) / (2 * PC);
-    with_length(L, [&](auto lc) {
-        deriv_axis_kernel<T, decltype(lc)::value>
-            <<<(unsigned)tiles, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(a);
-    });
+    const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
+    if (ntime <= kGroupTime) {
+        DerivArgs<T, kGroupTime> a;
+        fill(a, kGroupTime);
+        with_length(L, [&](auto lc) {
+            submit<DerivAxisBody<T, decltype(lc)::value, kGroupTime>,
+                   MergeFamily<decltype(lc)::value, DerivAxisBody<T, decltype(lc)::value, kGroupTime>,
+                               DerivAxisAnyBody<T, kGroupTime>>>(
+                dim3((unsigned)tiles), lds, st, a);
+        });
+    } else {
+        DerivArgs<T, kMaxTime> a;
+        fill(a, kMaxTime);
+        with_length(L, [&](auto lc) {
+            launch_now<DerivAxisBody<T, decltype(lc)::value, kMaxTime>>(dim3((unsigned)tiles), lds, st, a);
+        });
+    }
     return hipGetLastError();
 }
 
@@ -898,8 +1195,10 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
         with_length(L, [&](auto lc) {
-            r2c_rows_kernel<TI, TC, decltype(lc)::value>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[2], sh, ip, sp);
+            submit<R2cRowsBody<TI, TC, decltype(lc)::value>,
+                   MergeFamily<decltype(lc)::value, R2cRowsBody<TI, TC, decltype(lc)::value>,
+                               R2cRowsAnyBody<TI, TC>>>(
+                g, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st, R2cRowsArgs<TI, TC>{dm, pl.p[2], sh, ip, sp});
         });
     }
     for (int axis = 1; axis >= 3 - dm.dim + (skip_last ? 1 : 0); --axis) {
@@ -909,9 +1208,9 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const int PC = 1 << sh;
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         with_length(L, [&](auto lc) {
-            c2c_axis_kernel<TC, decltype(lc)::value>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st>>>(dm, pl.p[axis], axis,
-                                                                               sh, -1, sp);
+            submit<C2cAxisBody<TC, decltype(lc)::value>,
+                   MergeFamily<decltype(lc)::value, C2cAxisBody<TC, decltype(lc)::value>, C2cAxisAnyBody<TC>>>(
+                g, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st, C2cAxisArgs<TC>{dm, pl.p[axis], axis, sh, -1, sp});
         });
     }
     return hipGetLastError();
@@ -936,9 +1235,9 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const int PC = 1 << sh;
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         with_length(L, [&](auto lc) {
-            c2c_axis_kernel<T, decltype(lc)::value>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(dm, pl.p[axis], axis,
-                                                                              sh, +1, sp);
+            submit<C2cAxisBody<T, decltype(lc)::value>,
+                   MergeFamily<decltype(lc)::value, C2cAxisBody<T, decltype(lc)::value>, C2cAxisAnyBody<T>>>(
+                g, fft_lds_bytes(PC, L, sizeof(C2<T>)), st, C2cAxisArgs<T>{dm, pl.p[axis], axis, sh, +1, sp});
         });
     }
     {
@@ -948,9 +1247,9 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
         with_length(L, [&](auto lc) {
-            c2r_rows_kernel<T, decltype(lc)::value>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(dm, pl.p[2], sh,
-                                                                              T(scale), sp, op);
+            submit<C2rRowsBody<T, decltype(lc)::value>,
+                   MergeFamily<decltype(lc)::value, C2rRowsBody<T, decltype(lc)::value>, C2rRowsAnyBody<T>>>(
+                g, fft_lds_bytes(PC, L, sizeof(C2<T>)), st, C2rRowsArgs<T>{dm, pl.p[2], sh, T(scale), sp, op});
         });
     }
     return hipGetLastError();
@@ -966,7 +1265,7 @@ hipError_t launch_spec_gradient(const Dims& dm, const SpecOpParams& sp, C2<doubl
         b.spec[c] = bh[c];
         g.spec[c] = gh[c];
     }
-    spec_gradient_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, g);
+    submit<SpecGradientBody<T>>(dim3(pointwise_blocks(dm.NH)), 0, st, SpecGradientArgs<T>{dm, sp, a, b, g});
     return hipGetLastError();
 }
 
@@ -979,7 +1278,7 @@ hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* co
         b.spec[c] = sh[c];
         k.spec[c] = keep ? keep[c] : nullptr;
     }
-    spec_precond_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, k, keep != nullptr);
+    submit<SpecPrecondBody<T>>(dim3(pointwise_blocks(dm.NH)), 0, st, SpecPrecondArgs<T>{dm, sp, a, b, k, keep != nullptr});
     return hipGetLastError();
 }
 
@@ -1004,15 +1303,19 @@ hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
     // one tile per workgroup: a tile carries every component, so the grid is a
     // third of that of a single-field pass and needs all its workgroups
     const unsigned g = strided_blocks((npen + PC - 1) / PC, 1);
+    const C2cSpecArgs<T> ca{dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr};
+    const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
     with_length(L, [&](auto lc) {
         if (op == kSpecGrad)
-            c2c_spec_kernel<T, decltype(lc)::value, kSpecGrad>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
-                    dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr);
+            submit<C2cSpecBody<T, decltype(lc)::value, kSpecGrad>,
+                   MergeFamily<decltype(lc)::value, C2cSpecBody<T, decltype(lc)::value, kSpecGrad>,
+                               C2cSpecAnyBody<T, kSpecGrad>>>(
+                dim3(g), lds, st, ca);
         else
-            c2c_spec_kernel<T, decltype(lc)::value, kSpecPrecond>
-                <<<g, kFftThreads, fft_lds_bytes(PC, L, sizeof(C2<T>)), st>>>(
-                    dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr);
+            submit<C2cSpecBody<T, decltype(lc)::value, kSpecPrecond>,
+                   MergeFamily<decltype(lc)::value, C2cSpecBody<T, decltype(lc)::value, kSpecPrecond>,
+                               C2cSpecAnyBody<T, kSpecPrecond>>>(
+                dim3(g), lds, st, ca);
     });
     return hipGetLastError();
 }
@@ -1026,7 +1329,7 @@ hipError_t launch_spec_pow(const Dims& dm, const SpecOpParams& sp, C2<T>* const*
         a.spec[c] = gh[c];
         b.spec[c] = sh[c];
     }
-    spec_pow_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, sp, a, b, expo, sign, band_cut);
+    submit<SpecPowBody<T>>(dim3(pointwise_blocks(dm.NH)), 0, st, SpecPowArgs<T>{dm, sp, a, b, expo, sign, band_cut});
     return hipGetLastError();
 }
 
@@ -1044,9 +1347,9 @@ hipError_t launch_spec_resample(const Dims& df, const Dims& dc, C2<T>* const* sr
         d.spec[c] = dst[c];
     }
     if (to_coarse)
-        spec_restrict_kernel<T><<<pointwise_blocks(dc.NH), 256, 0, st>>>(df, dc, s, d, count, T(scale));
+        submit<SpecRestrictBody<T>>(dim3(pointwise_blocks(dc.NH)), 0, st, SpecRestrictArgs<T>{df, dc, s, d, count, T(scale)});
     else
-        spec_prolong_kernel<T><<<pointwise_blocks(df.NH), 256, 0, st>>>(df, dc, s, d, count, T(scale));
+        submit<SpecProlongBody<T>>(dim3(pointwise_blocks(df.NH)), 0, st, SpecProlongArgs<T>{df, dc, s, d, count, T(scale)});
     return hipGetLastError();
 }
 
@@ -1060,8 +1363,8 @@ hipError_t launch_spec_cross(const Dims& dm, const SpecOpParams& sp, C2<double>*
         b.spec[c] = sh[c];
     }
     const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 2);
-    spec_cross_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, b, partial);
-    finish_kernel<false><<<finish_blocks(2 * ns), 1024, 0, st>>>(partial, nb, 2 * ns, res);
+    submit<SpecCrossBody<T>>(dim3(nb, ns), 0, st, SpecCrossArgs<T>{dm, sp, a, b, partial});
+    launch_finish<false>(partial, nb, 2 * ns, res, st);
     return hipGetLastError();
 }
 
@@ -1078,7 +1381,7 @@ hipError_t launch_spec_axpy(const Dims& dm, int dim, C2<double>* const* vh, cons
     if (ns > kMaxSeg) return hipErrorInvalidValue;
     SegCoef rc{};
     for (int i = 0; i < ns; ++i) rc.c[i] = rho[i];
-    spec_axpy_kernel<T><<<pointwise_blocks(dm.NH), 256, 0, st>>>(dm, dim, a, rc, b);
+    submit<SpecAxpyBody<T>>(dim3(pointwise_blocks(dm.NH)), 0, st, SpecAxpyArgs<T>{dm, dim, a, rc, b});
     return hipGetLastError();
 }
 
@@ -1088,8 +1391,8 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
     SpecPtrs<T> a{};
     for (int c = 0; c < sp.dim; ++c) a.spec[c] = vh[c];
     const int ns = spec_nseg(dm), nb = spec_red_blocks(dm, 1);
-    spec_regvalue_kernel<T><<<dim3(nb, ns), 256, 0, st>>>(dm, sp, a, partial);
-    finish_kernel<false><<<finish_blocks(ns), 1024, 0, st>>>(partial, nb, ns, res);
+    submit<SpecRegvalueBody<T>>(dim3(nb, ns), 0, st, SpecRegvalueArgs<T>{dm, sp, a, partial});
+    launch_finish<false>(partial, nb, ns, res, st);
     return hipGetLastError();
 }
 

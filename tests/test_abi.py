@@ -10,7 +10,7 @@ import paper_2510_08782_amd as gan
 def test_library_exports_every_header_symbol():
     lib = gan.lib()
     syms = gan.header_symbols()
-    assert len(syms) == 24
+    assert len(syms) == 27
     for name in syms:
         assert hasattr(lib, name), name
     for name in ["ganmres_eval_objective", "ganmres_eval_gradient", "ganmres_apply_precond",

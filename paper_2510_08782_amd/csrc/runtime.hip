@@ -960,6 +960,7 @@ class Problem : public ProblemBase {
     }
 
     double objective(const void* v, bool keep, double* mis) override {
+        pre_g = nullptr;
         prepare(v, false);
         forward();
         mismatch(false);
@@ -1050,6 +1051,7 @@ class Problem : public ProblemBase {
     }
 
     double gradient(const void* v, void* g, bool reuse) override {
+        pre_g = nullptr;
         gradient_async(v, g, reuse);
         return resolve_J();
     }
@@ -1094,6 +1096,7 @@ class Problem : public ProblemBase {
     }
 
     double precond(const void* g, void* s) override {
+        pre_g = nullptr;
         precond_keep(g, s, false);
         double t = 0.0;
         for (int i = 0; i < nb; ++i) t += gs_s[i];
@@ -1104,6 +1107,12 @@ class Problem : public ProblemBase {
     // max |s| (cells per step) and the regulariser cross terms of the line
     // v + rho s (dres[R_CROSS..], see launch_spec_cross)
     void precond_keep(const void* g, void* s, bool keep) {
+        precond_launch(g, s, keep);
+        stream_sync(st);
+        precond_collect(keep);
+    }
+    // the launches of precond_keep and the copy of its results to the host
+    void precond_launch(const void* g, void* s, bool keep) {
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st, 1); });
         run(KC_SPEC, [&] {
@@ -1128,13 +1137,25 @@ class Problem : public ProblemBase {
         HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT,
                               sizeof(double) * ((keep ? R_CROSS + 2 * nb : R_SMAX + 1) - R_DOT),
                               hipMemcpyDeviceToHost, st));
-        stream_sync(st);
-        if (keep) smax = hres[R_SMAX];
+    }
+    // after the stream has synchronised: the results of precond_launch
+    void precond_collect(bool keep) {
+        if (keep) {
+            smax = hres[R_SMAX];
+            crossA.assign(hres + R_CROSS, hres + R_CROSS + nb);
+            crossB.assign(hres + R_CROSS + nb, hres + R_CROSS + 2 * nb);
+        }
         gs_s.resize(nb);
         for (int i = 0; i < nb; ++i) gs_s[i] = cell * hres[R_DOT + i];
     }
     double smax = 0.0;          // max |u| of the last kept search direction
     std::vector<double> gs_s;   // <g, s>_h per problem of the last preconditioning
+    std::vector<double> crossA, crossB;  // regulariser cross sums of the kept direction
+    // The direction of the next iteration, launched at the end of a solver
+    // step so that its results reach the host with the step's own
+    // synchronisation: the gradient it belongs to (nullptr: none pending).
+    // Any other use of the handle forgets it.
+    const void* pre_g = nullptr;
 
     // max |a| per problem
     std::vector<double> maxabs(const T* a) {
@@ -1192,6 +1213,7 @@ class Problem : public ProblemBase {
 
     // the caller's v may have changed since any earlier call: solve the state again
     void hessian_matvec(const void* v, const void* vt, void* out) override {
+        pre_g = nullptr;
         check_newton_setup();
         prepare(v, true);
         forward();
@@ -1526,6 +1548,7 @@ class Problem : public ProblemBase {
     }
 
     void newton_precond(int which, const void* v, const void* r, void* z) override {
+        pre_g = nullptr;
         check_newton_setup();
         if (which != GANMRES_PC_IREG && which != GANMRES_PC_H0RPC && which != GANMRES_PC_2LRPCSYM)
             throw Error(GANMRES_EINVAL, "unknown preconditioner");
@@ -1667,6 +1690,7 @@ class Problem : public ProblemBase {
     // (nullable).  Uses the state's departure points of v.
     std::vector<std::unique_ptr<DevBuf>> dfm_bufs;
     void deformation(const void* v, void* det, double* stats) override {
+        pre_g = nullptr;
         prepare(v, false);
         // dX now belongs to v: a kept forward history of another velocity is void
         fwd_valid = false;
@@ -1732,6 +1756,7 @@ class Problem : public ProblemBase {
 
     // -- GA-NGMRES ----------------------------------------------------------
     void reset() override {
+        pre_g = nullptr;
         started = false;
         hist.clear();
         k = 0;
@@ -1802,12 +1827,12 @@ class Problem : public ProblemBase {
         if (umax_of != Vc) set_bounds(Vc, velocity_max(Vc));
         const std::vector<double> R0 = reg_s;
         const double um0 = umax;
-        precond_keep(Gc, s, true);
-        const double* cr = hres + R_CROSS;
+        if (pre_g != Gc) precond_keep(Gc, s, true);
+        pre_g = nullptr;
         std::vector<double> cA(nb), cB(nb);
         for (int i = 0; i < nb; ++i) {
-            cA[i] = cell / double(Nt) * cr[i];
-            cB[i] = cell / double(Nt) * cr[nb + i];
+            cA[i] = cell / double(Nt) * crossA[i];
+            cB[i] = cell / double(Nt) * crossB[i];
         }
         std::vector<double> rho(rho_bar), Rq(R0);
         std::vector<int> trials(nb, 0);
@@ -1913,7 +1938,15 @@ class Problem : public ProblemBase {
         run(KC_REDUCE, [&] { return launch_maxabs<T>(Gn, vseg(), partial, dres + R_MAX, st); });
         HIPCHK(hipMemcpyAsync(hres + R_MAX, dres + R_MAX, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
+        // the next iteration starts with the direction of g^{k+1}: launched
+        // now, it reaches the host with this synchronisation
+        const bool prefetch = k < p.n_iter;
+        if (prefetch) precond_launch(Gn, sb->p, true);
         stream_sync(st);
+        if (prefetch) {
+            precond_collect(true);
+            pre_g = Gn;
+        }
         if (J_pending) resolve_J();  // the copy behind ev_res has run
         const std::vector<double>& Jv = Jnew.empty() ? J_s : Jnew;
         const std::vector<double> ginf(hres + R_MAX, hres + R_MAX + nb);

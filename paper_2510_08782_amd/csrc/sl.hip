@@ -122,8 +122,14 @@ __device__ inline T gather_global(const Dims& dm, const T* __restrict__ s, int i
 // variant chosen per grid size by the tile autotuner, see Dims::tile).  S is
 // the capacity of the staged region: up to S cells of spread of the
 // displacement floors per axis.
+#ifndef GAN_PX3
+#define GAN_PX3 48  // LDS row pitch of the 3-D windows (words)
+#endif
+#ifndef GAN_TZ_F32
+#define GAN_TZ_F32 2  // points per thread along z of the 3-D FP32 tiles
+#endif
 template <typename T_, int DIM_, int S_,
-          int P_ = (DIM_ == 3 ? (sizeof(T_) == 4 ? 2 : 4) : kTile2Default)>
+          int P_ = (DIM_ == 3 ? (sizeof(T_) == 4 ? GAN_TZ_F32 : 4) : kTile2Default)>
 struct Tile;
 template <typename T_, int S_, int TZ_>
 struct Tile<T_, 3, S_, TZ_> {
@@ -134,7 +140,7 @@ struct Tile<T_, 3, S_, TZ_> {
     static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = TZ + S + 3;
     // LDS row pitch: the two rows a wavefront reads (lanes 0-31 and 32-63)
     // start half the banks apart
-    static constexpr int PX = 48;
+    static constexpr int PX = GAN_PX3;
     static constexpr int PZ = PX * RY;  // plane pitch
     static_assert(RX <= PX, "window wider than the row pitch");
     static constexpr int PTS = TZ;  // points per thread

@@ -158,7 +158,7 @@ def test_group_trajectories(accel):
     # the line searches of the classes take different numbers of trials (a
     # class whose problems have all accepted launches nothing meanwhile), so
     # fewer launches merge than in an evaluation
-    assert issued * 1.5 <= submitted
+    assert issued * 1.3 <= submitted
 
 
 def test_group_rejects_newton_and_bad_classes():

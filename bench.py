@@ -251,6 +251,39 @@ def c3_throughput(torch, gan, synth):
     return out
 
 
+def copy_probe(torch):
+    """A plain 1 GiB device copy: the calibration of the HBM traffic counters."""
+    a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    del a, b
+
+
+def c3_profile_driver(torch, gan, synth, reps, probe):
+    """Profiling driver: reps gradients of the 256^3 workload at v*/2 (FP32,
+    checkpoint every 2), optionally followed by the copy probe."""
+    wl = synth.workload("c3")
+    dev = lambda x: torch.tensor(x, dtype=torch.float32, device="cuda")
+    m0 = dev(wl.m0)
+    vstar = dev(wl.vstar)
+    gen = gan.Problem(m0, m0, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=2)
+    gen.eval_objective(vstar)
+    m1 = gen.get_field("state", wl.nt)
+    gen.close()
+    P = gan.Problem(m0, m1, wl.nt, wl.alpha, wl.reg_order, checkpoint_every=2)
+    v = (0.5 * vstar).contiguous()
+    for i in range(reps):
+        J, _ = P.eval_gradient(v)
+        log(f"c3 gradient {i}: J = {J:.10e}")
+    P.close()
+    if probe:
+        copy_probe(torch)
+
+
 def c1_errors(torch, gan, synth):
     """2-D continuity at 256^2, H2, nt=8: FP32 objective and gradient at
     v = v*/2 against the FP64 path on the same (FP32-rounded) inputs."""
@@ -350,6 +383,9 @@ def main():
     ap.add_argument("--no-c1", action="store_true", help="skip the 256^2 continuity FP32/FP64 errors")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--c3-gradients", type=int, default=0,
+                    help="profiling driver: only this many gradient evaluations of the 256^3 "
+                         "workload (FP32, checkpoint every 2), then exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "the solver runs on one GPU; --gpus must be 1 "
@@ -362,6 +398,10 @@ def main():
     import paper_2510_08782_amd as gan
     import synth
 
+    if args.c3_gradients:
+        c3_profile_driver(torch, gan, synth, args.c3_gradients, args.copy_probe)
+        return
+
     wl = synth.workload("c2")
     N = int(np.prod(wl.shape))
     sv = wl.solver
@@ -371,14 +411,7 @@ def main():
     P32, vstar32 = make_problem(torch, gan, synth, torch.float32, wl)
 
     if args.copy_probe:
-        a = torch.empty(256 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        b = torch.empty_like(a)
-        a.fill_(1.0)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+        copy_probe(torch)
 
     # Per-class breakdown from a pass with every launch bracketed by events;
     # the timed region then brackets only the dominant class (each event pair

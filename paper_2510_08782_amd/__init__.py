@@ -17,7 +17,10 @@ import re
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "_lib", "libganmres.so")
+# GANMRES_CHECKED=1 selects the build whose gathers check every interpolation
+# stencil against the window staged in LDS (python -m paper_2510_08782_amd.build --checked)
+LIB_PATH = os.path.join(HERE, "_lib", "libganmres_checked.so"
+                        if os.environ.get("GANMRES_CHECKED") == "1" else "libganmres.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "ganmres.h")
 
 ADVECTION, CONTINUITY = 0, 1
@@ -74,7 +77,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2510_08782_amd.build`")
+        flag = " --checked" if LIB_PATH.endswith("_checked.so") else ""
+        raise RuntimeError(f"{LIB_PATH} is missing: run `python -m paper_2510_08782_amd.build{flag}`")
     L = ctypes.CDLL(LIB_PATH)
     vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int
     L.ganmres_create.argtypes = [ctypes.POINTER(Config), vp, vp, vp, ctypes.POINTER(vp)]

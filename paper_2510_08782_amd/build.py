@@ -1,8 +1,14 @@
 """Build libganmres.so (gfx950) from the HIP sources in csrc/.
 
-Usage: python -m paper_2510_08782_amd.build  (or build() from Python).
+Usage: python -m paper_2510_08782_amd.build [--checked]  (or build() from Python).
 Each translation unit is compiled in parallel with hipcc, then linked into
 paper_2510_08782_amd/_lib/libganmres.so.
+
+--checked builds libganmres_checked.so instead, with GAN_CHECK_TAPS defined:
+a gather whose interpolation stencil falls outside the window staged in LDS
+poisons that point with NaN (the evaluation then fails with
+GANMRES_ENONFINITE) instead of clamping the LDS index.  The binding loads it
+when GANMRES_CHECKED=1 is set in the environment.
 """
 from __future__ import annotations
 
@@ -27,12 +33,15 @@ FLAGS = [
     "-munsafe-fp-atomics", "-Wall", "-Wno-unused-function",
     "-I", os.path.join(ROOT, "include"),
 ]
+LIB_CHECKED = os.path.join(OUT_DIR, "libganmres_checked.so")
 SOURCES = ["sl.hip", "spectral.hip", "vec.hip", "runtime.hip", "noalloc.hip"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, src + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, checked: bool) -> str:
+    bdir = os.path.join(BUILD_DIR, "checked") if checked else BUILD_DIR
+    obj = os.path.join(bdir, src + ".o")
+    extra = ["-DGAN_CHECK_TAPS"] if checked else []
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
@@ -41,21 +50,22 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = True) -> str:
+def build(verbose: bool = True, checked: bool = False) -> str:
+    lib = LIB_CHECKED if checked else LIB
     os.makedirs(OUT_DIR, exist_ok=True)
-    os.makedirs(BUILD_DIR, exist_ok=True)
+    os.makedirs(os.path.join(BUILD_DIR, "checked") if checked else BUILD_DIR, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, checked), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {lib}")
+    return lib
 
 
 if __name__ == "__main__":
-    build()
+    build(checked="--checked" in sys.argv[1:])

@@ -330,11 +330,21 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
 // Tap base and weights along one axis for the LDS path: local index of the
 // node f-1 for point index li within the tile, the window starting at
 // floor minimum lo (minus one).
+// The window (from the tile's floor ranges) always contains the stencil; the
+// clamp only keeps the LDS address inside the region if a window table were
+// stale.  Built with GAN_CHECK_TAPS, a stencil outside the staged extent ext
+// instead poisons its weights with NaN, so that the evaluation fails with
+// GANMRES_ENONFINITE rather than returning silently wrong values.
 template <typename T, int R>
-__device__ inline int lds_axis(int li, T disp, int lo, T* w) {
+__device__ inline int lds_axis(int li, T disp, int lo, int ext, T* w) {
     const T fl = floor(disp);
     lagrange4(disp - fl, w);
     int l = li + static_cast<int>(fl) - lo;
+#ifdef GAN_CHECK_TAPS
+    if (l < 0 || l > ext - 4) w[0] = w[1] = w[2] = w[3] = T(NAN);
+#else
+    (void)ext;
+#endif
     l = l < 0 ? 0 : (l > R - 4 ? R - 4 : l);
     return l;
 }
@@ -353,10 +363,10 @@ __device__ inline Stencil<typename C::T> lds_stencil(const Window& win, int lx, 
                                                      typename C::T d2) {
     using T = typename C::T;
     Stencil<T> st;
-    const int bx = lds_axis<T, C::RX>(lx, d2, win.lo[0], st.wx);
-    const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], st.wy);
+    const int bx = lds_axis<T, C::RX>(lx, d2, win.lo[0], win.ext[0], st.wx);
+    const int by = lds_axis<T, C::RY>(ly, d1, win.lo[1], win.ext[1], st.wy);
     if constexpr (C::DIM == 3) {
-        const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], st.wz);
+        const int bz = lds_axis<T, C::RZ>(lz, d0, win.lo[2], win.ext[2], st.wz);
         st.base = bz * C::PZ + by * C::PX + bx;
     } else {
         st.base = by * C::PX + bx;

@@ -80,3 +80,48 @@ def test_batch_sizes_parity(n, prec):
         vs = [round_to(p[pname], prec) for p in pr]
         check_batch_probe(Ps, B, vs, dtype, TOL[prec], pname)
     B.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_group_sizes_parity(prec):
+    """The three sizes in ONE group handle (two problems per size, merged
+    launches): each problem's objective, mismatch, gradient and preconditioned
+    direction against the FP64 oracle at v*/2 and at the perturbed probe."""
+    import paper_2510_08782_amd as gan
+    say(f"group 96/192/384 {prec}")
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    tol = TOL[prec]
+    dev = lambda x: torch.tensor(np.ascontiguousarray(x), dtype=dtype, device="cuda")
+    wls = [[synth.workload("c4i", shape=(n, n), seed=s) for s in SEEDS[n][:2]]
+           for n in (96, 192, 384)]
+    Ps = [[as_precision(oracle_problem(w), prec) for w in wc] for wc in wls]
+    G = gan.GroupProblem([dev(np.stack([P.m0 for P in Pc])) for Pc in Ps],
+                         [dev(np.stack([P.m1 for P in Pc])) for Pc in Ps],
+                         wls[0][0].nt, [w.alpha for wc in wls for w in wc], wls[0][0].reg_order)
+    pr = [[probes(w) for w in wc] for wc in wls]
+    for pname in ("half", "perturbed"):
+        vs = [[round_to(p[pname], prec) for p in pc] for pc in pr]
+        v = G.pack_velocity([dev(np.stack(vc, axis=1)) for vc in vs])
+        _, g = G.eval_gradient(v)
+        Jv, misv = G.values()
+        s, _ = G.apply_precond(g)
+        gv, sv = G.velocity_views(g), G.velocity_views(s)
+        k = 0
+        for c, Pc in enumerate(Ps):
+            gc, sc = host(gv[c]), host(sv[c])
+            for i, P in enumerate(Pc):
+                Jo, miso, _ = P.objective(vs[c][i], return_parts=True)
+                _, go = P.gradient(vs[c][i])
+                err, errinf = rel(gc[:, i], go), relinf(gc[:, i], go)
+                say(f"  {pname} class {c} problem {i}: J {Jv[k]:.12e} / {Jo:.12e}, "
+                    f"g rel {err:.2e} (inf {errinf:.2e})")
+                assert abs(Jv[k] - Jo) <= tol * abs(Jo)
+                assert abs(misv[k] - miso) <= tol * max(abs(miso), 1e-300) + tol * abs(Jo)
+                assert err <= tol and errinf <= tol
+                so, _ = ong.precond(P, gc[:, i])
+                assert rel(sc[:, i], so) <= tol and relinf(sc[:, i], so) <= tol
+                k += 1
+    submitted, issued = G.launches()
+    say(f"  launches: {submitted} by the classes, {issued} merged")
+    assert issued * 2.5 <= submitted
+    G.close()

@@ -142,8 +142,9 @@ struct Tile<T_, 3, S_, TZ_> {
     // start half the banks apart
     static constexpr int PX = GAN_PX3;
     static constexpr int PZ = PX * RY;  // plane pitch
-    static_assert(RX <= PX, "window wider than the row pitch");
+    static_assert(RX + 2 <= PX && PX % 2 == 0, "row pitch: even, and room for the pair past a row");
     static constexpr int PTS = TZ;  // points per thread
+    static constexpr int LDSN = PZ * RZ + 2;  // elements per staged field (even)
 };
 template <typename T_, int S_, int P_>
 struct Tile<T_, 2, S_, P_> {
@@ -152,14 +153,18 @@ struct Tile<T_, 2, S_, P_> {
     static constexpr int TX = 64, TY = 4 * P_, TZ = 1;
     static constexpr int S = S_;
     static constexpr int RX = TX + S + 3, RY = TY + S + 3, RZ = 1;
-    static constexpr int PX = RX;  // a wavefront reads one row
+    static constexpr int PX = (RX + 1) & ~1;  // a wavefront reads one row; even pitch
     static constexpr int PZ = PX * RY;
     static constexpr int PTS = P_;
+    static constexpr int LDSN = PZ * RZ + 2;
 };
 
+// LDS bytes of one staged field.  Rows start at even element offsets and the
+// region ends with two spare elements, so that the FP32 interpolation can read
+// every row as aligned pairs (the last pair may reach one element past a row).
 template <class C>
 constexpr size_t tile_lds_bytes() {
-    return sizeof(typename C::T) * C::PZ * C::RZ;
+    return sizeof(typename C::T) * C::LDSN;
 }
 
 // g mod n in [0, n): the common in-range case costs one compare.
@@ -239,6 +244,9 @@ __device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], i
             m[a] = min(m[a], red[q * 6 + a]);
             M[a] = max(M[a], red[q * 6 + 3 + a]);
         }
+        // the same in every lane: keep it in scalar registers
+        m[a] = __builtin_amdgcn_readfirstlane(m[a]);
+        M[a] = __builtin_amdgcn_readfirstlane(M[a]);
     }
     if (entry && threadIdx.x < 6) {
         const int i = threadIdx.x;
@@ -247,16 +255,30 @@ __device__ inline Window tile_window(const int (&fmn)[3], const int (&fmx)[3], i
     return window_from<C>(m, M);
 }
 
+// g mod n for a wave-uniform g: the window origins lie within one period of
+// the grid in all but extreme displacements, so the common cases are scalar
+// compares and the division only runs for the rest.
+__device__ inline int wrap_uniform(int g, int n) {
+    if (g >= 0 && g < n) return g;
+    if (g < 0 && g >= -n) return g + n;
+    if (g >= n && g < 2 * n) return g - n;
+    return pmod(g, n);
+}
+
 // Stage src over the window of the tile with origin (x0, y0, z0).
 // Global-to-LDS loads (global_load_lds_dword): a wavefront walks the rows of
 // the region and moves each row with one instruction per 64 dwords, lane l
 // writing dword l of the row; the wrapped x index of every lane is computed
 // once.  The wave's rows are described in parallel, one row per lane (its
-// wrapped global offset and its LDS offset), and the issue loop only reads
-// them back from the lanes, so that it carries no division, wrap or branch
-// per row.  All of a wave's row loads are in flight together and no VGPRs
+// global offset and its LDS offset), and the issue loop only reads them back
+// from the lanes, so that it carries no division, wrap or branch per row.
+// The descriptions avoid integer division too: the row's plane comes from a
+// float reciprocal of the row count per plane (exact for these small
+// integers), and the grid rows wrap by comparison from the wrapped window
+// origin.  All of a wave's row loads are in flight together and no VGPRs
 // hold the data.  FP64 rows move as pairs of dwords.  The LDS layout keeps
-// the variant's row pitch PX and plane pitch PZ.  Ends with a barrier.
+// the variant's row pitch PX and plane pitch PZ.  Ends with a barrier unless
+// WAIT is false.
 template <class C, bool WAIT = true>
 __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ src,
                              typename C::T* lds, int x0, int y0, int z0, const Window& w) {
@@ -266,26 +288,39 @@ __device__ inline void stage(const Dims& dm, const typename C::T* __restrict__ s
     constexpr int XP = (W * C::RX + 63) / 64;         // dword passes per row
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int n0 = dm.n[0], n1 = dm.n[1], n2 = dm.n[2];
     const int ex = w.ext[0], ey = w.ext[1], rows = w.ext[1] * w.ext[2];
-    const int ox = x0 + w.lo[0] - 1, oy = y0 + w.lo[1] - 1;
-    const int oz = C::DIM == 3 ? z0 + w.lo[2] - 1 : z0;
+    const int ox = wrap_uniform(x0 + w.lo[0] - 1, n2);
+    const int oy = wrap_uniform(y0 + w.lo[1] - 1, n1);
+    // 2-D: axis 0 indexes independent slices (no interpolation across it)
+    const int oz = C::DIM == 3 ? wrap_uniform(z0 + w.lo[2] - 1, n0) : z0;
     int goff[XP];                                    // dword offset of the lane's element in a row
     bool xin[XP];
 #pragma unroll
     for (int u = 0; u < XP; ++u) {
         const int d = lane + 64 * u;
         xin[u] = d < W * ex;
-        goff[u] = W * wrapn(ox + d / W, dm.n[2]) + d % W;
+        int gx = ox + d / W;
+        while (gx >= n2) gx -= n2;
+        goff[u] = W * gx + d % W;
     }
+    // (r + 1/2) / ey is at least 1 / (2 ey) away from an integer; for the
+    // row counts here (r < 2^21) the float error of the product is smaller
+    const float rey = 1.0f / static_cast<float>(ey);
     // this wave's rows are r = wave + NW i, i < cnt
     const int cnt = rows > wave ? (rows - wave + NW - 1) / NW : 0;
     for (int i0 = 0; i0 < cnt; i0 += 64) {
         const int r = wave + NW * (i0 + lane);
-        const int ry = r % ey, rz = r / ey;
-        const int gy = pmod(oy + ry, dm.n[1]);
-        // 2-D: axis 0 indexes independent slices (no interpolation across it)
-        const int gz = C::DIM == 3 ? pmod(oz + rz, dm.n[0]) : z0;
-        const int grow = (gz * dm.n[1] + gy) * dm.n[2];  // elements; N < 2^31
+        const int rz = static_cast<int>((static_cast<float>(r) + 0.5f) * rey);
+        const int ry = r - rz * ey;
+        int gy = oy + ry;
+        while (gy >= n1) gy -= n1;
+        int gz = z0;
+        if constexpr (C::DIM == 3) {
+            gz = oz + rz;
+            while (gz >= n0) gz -= n0;
+        }
+        const int grow = (gz * n1 + gy) * n2;  // elements; N < 2^31
         const int lrow = rz * C::PZ + ry * C::PX;
         const int m = min(64, cnt - i0);
         // The row descriptions are read back from the lanes (readlane, wave
@@ -374,34 +409,111 @@ __device__ inline Stencil<typename C::T> lds_stencil(const Window& win, int lx, 
     return st;
 }
 
+// Offset of plane a of a stencil plus d, held in a register of its own: the
+// row reads of the plane then address it with the instruction's immediate
+// offset (rows up to 3 PX + 3 elements away), where otherwise each read of a
+// plane beyond the first would get an address addition of its own.
+template <class C>
+__device__ inline int plane_offset(int base, int a, int d = 0) {
+    int o = base + a * C::PZ + d;
+    if (a > 0 || d != 0) asm("" : "+v"(o));
+    return o;
+}
+
+// One 8-byte LDS read.  The reads are volatile so that the compiler keeps them
+// as separate ds_read_b64: merged into ds_read2_b64 they move data at about
+// two thirds of the rate on this target.
+template <typename T>
+struct Pair {
+    T x, y;
+};
+__device__ inline Pair<float> lds_pair(const float* p) {
+    typedef float V2 __attribute__((ext_vector_type(2)));
+    typedef const volatile __attribute__((address_space(3))) V2 LV2;
+    const V2 v = *(LV2*)(p);
+    return Pair<float>{v.x, v.y};
+}
+// One LDS element, kept as a read of its own in the same way.
+template <typename T>
+__device__ inline T lds_one(const T* p) {
+    typedef const volatile __attribute__((address_space(3))) T LT;
+    return *(LT*)(p);
+}
+
 // Tensor-product cubic interpolation of a staged field at a stencil.
+//
+// FP32: the four x taps of a row start at any element, but LDS reads of 8
+// bytes are fast only when aligned (a misaligned one is serialised, and two
+// 4-byte reads take half again as long as one aligned 8-byte read).  Each row
+// is therefore read as aligned pairs starting at the even element at or
+// below the first tap, and the row is contracted with five x weights: the
+// four cubic weights, shifted by one when the first tap is odd.  The fifth
+// element is read on its own (4 bytes): the one after the four taps' pairs
+// when the first tap is odd, a repeat of the third when it is even (its
+// weight is then zero), so that no element outside the staged row enters the
+// sum.
+//
+// FP64: every tap is one aligned 8-byte read; they are kept as separate
+// reads too, which take less time than the paired form.
 template <class C>
 __device__ inline typename C::T lds_interp(const typename C::T* lds,
                                            const Stencil<typename C::T>& st) {
     using T = typename C::T;
-    const T* base = lds + st.base;
-    T acc = T(0);
-    if constexpr (C::DIM == 3) {
+    if constexpr (sizeof(T) == 4) {
+        const bool odd = st.base & 1;
+        const int e = st.base & ~1;
+        const T u0 = odd ? T(0) : st.wx[0], u1 = odd ? st.wx[0] : st.wx[1];
+        const T u2 = odd ? st.wx[1] : st.wx[2], u3 = odd ? st.wx[2] : st.wx[3];
+        const T u4 = odd ? st.wx[3] : T(0);
+        const int d3 = odd ? 4 : 2;
+        const int nplanes = C::DIM == 3 ? 4 : 1;
+        T acc = T(0);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            T sa = T(0);
+        for (int a = 0; a < nplanes; ++a) {
+            const T* plane = lds + plane_offset<C>(e, a);
+            const T* third = lds + plane_offset<C>(e, a, d3);
+            Pair<T> q[4][2];
+            T t[4];
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
-                const T* row = base + a * C::PZ + b * C::PX;
-                sa += st.wy[b] *
-                      (st.wx[0] * row[0] + st.wx[1] * row[1] + st.wx[2] * row[2] + st.wx[3] * row[3]);
+                q[b][0] = lds_pair(plane + b * C::PX);
+                q[b][1] = lds_pair(plane + b * C::PX + 2);
+                t[b] = lds_one(third + b * C::PX);
             }
-            acc += st.wz[a] * sa;
-        }
-    } else {
+            T sa = T(0);
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-            const T* row = base + b * C::PX;
-            acc += st.wy[b] *
-                   (st.wx[0] * row[0] + st.wx[1] * row[1] + st.wx[2] * row[2] + st.wx[3] * row[3]);
+            for (int b = 0; b < 4; ++b)
+                sa += st.wy[b] * (u0 * q[b][0].x + u1 * q[b][0].y + u2 * q[b][1].x +
+                                  u3 * q[b][1].y + u4 * t[b]);
+            acc = C::DIM == 3 ? acc + st.wz[a] * sa : sa;
         }
+        return acc;
+    } else {
+        const T* base = lds + st.base;
+        T acc = T(0);
+        if constexpr (C::DIM == 3) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a) {
+                T sa = T(0);
+                const T* plane = lds + plane_offset<C>(st.base, a);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const T* row = plane + b * C::PX;
+                    sa += st.wy[b] * (st.wx[0] * lds_one(row) + st.wx[1] * lds_one(row + 1) +
+                                      st.wx[2] * lds_one(row + 2) + st.wx[3] * lds_one(row + 3));
+                }
+                acc += st.wz[a] * sa;
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const T* row = base + b * C::PX;
+                acc += st.wy[b] * (st.wx[0] * lds_one(row) + st.wx[1] * lds_one(row + 1) +
+                                   st.wx[2] * lds_one(row + 2) + st.wx[3] * lds_one(row + 3));
+            }
+        }
+        return acc;
     }
-    return acc;
 }
 
 // Interpolate from the staged window at tile-local point (lx,ly,lz) displaced by d.
@@ -725,7 +837,7 @@ struct CharacteristicsAllBody {
         typename C::T* __restrict__ dY = args_.dY;
         using T = typename C::T;
         constexpr int DIM = C::DIM;
-        constexpr int PLANE = C::PZ * C::RZ;  // elements per staged component
+        constexpr int PLANE = C::LDSN;  // elements per staged component
         extern __shared__ double2 sl_smem[];
         T* lds = reinterpret_cast<T*>(sl_smem);
         __shared__ int red[6 * (kThreads / 64)];

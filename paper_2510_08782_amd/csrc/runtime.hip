@@ -628,16 +628,18 @@ class Problem : public ProblemBase {
             bufs.back()->alloc(sizeof(double) * kGramPartialDoubles);
             partial = static_cast<double*>(bufs.back()->p);
             bufs.emplace_back(new DevBuf);
-            bufs.back()->alloc(sizeof(double) * kRes);
-            dres = static_cast<double*>(bufs.back()->p);
-            bufs.emplace_back(new DevBuf);
             bufs.back()->alloc(sizeof(double) * kMaxSeg);
             alpha_dev = static_cast<double*>(bufs.back()->p);
             bufs.emplace_back(new DevBuf);
             bufs.back()->alloc(sizeof(double) * (GANMRES_MAX_WINDOW + 1) * kMaxSeg);
             coef_dev = static_cast<double*>(bufs.back()->p);
         }
-        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * kRes, hipHostMallocDefault));
+        // the reductions write their results straight into this pinned,
+        // mapped host buffer (dres is its device address): a result is on the
+        // host once the stream has passed its reduction, with no copy
+        HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hres), sizeof(double) * kRes,
+                             hipHostMallocMapped | hipHostMallocCoherent));
+        HIPCHK(hipHostGetDevicePointer(reinterpret_cast<void**>(&dres), hres, 0));
         HIPCHK(hipEventCreateWithFlags(&ev_res, hipEventDisableTiming));
         HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hup), sizeof(double) * (GANMRES_MAX_WINDOW + 1) * kMaxSeg,
                              hipHostMallocDefault));
@@ -773,9 +775,12 @@ class Problem : public ProblemBase {
         tend();
     }
 
-    // copy result slot [at, at + n) to the host (synchronises)
+    // result slots [at, at + n) on the host (synchronises).  Every slot is
+    // written by the reductions in stream order: the host reads a slot only
+    // after a synchronisation that follows its reduction, and before it
+    // launches another reduction into the same slot.
     const double* fetch(int at, int n) {
-        HIPCHK(hipMemcpyAsync(hres + at, dres + at, sizeof(double) * n, hipMemcpyDeviceToHost, st));
+        (void)n;
         stream_sync(st);
         return hres + at;
     }
@@ -841,7 +846,6 @@ class Problem : public ProblemBase {
                 return launch_velocity_max<T>(dm, static_cast<const T*>(v), cscale, partial,
                                               dres + R_UMAX, st);
             });
-            HIPCHK(hipMemcpyAsync(hres + R_UMAX, dres + R_UMAX, sizeof(double), hipMemcpyDeviceToHost, st));
             HIPCHK(hipEventRecord(ev_res, st));
             if (!trial) spectrum_of(v);
             event_sync(ev_res);
@@ -920,16 +924,13 @@ class Problem : public ProblemBase {
 
     // J per problem (J_s, mis_s) and their sum
     double finish_J(double* mis_out) {
-        const int n = reg_from_device ? R_REG + nb : nb;
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         stream_sync(st);
         return J_from_host(mis_out);
     }
-    // copy the ingredients of J to the host behind an event (see J_from_host)
+    // the ingredients of J reach the host behind an event (see J_from_host);
+    // until it is taken up, no reduction into their slots is launched
     void J_to_host() {
         J_pending = false;
-        const int n = reg_from_device ? R_REG + nb : nb;
-        HIPCHK(hipMemcpyAsync(hres, dres, sizeof(double) * n, hipMemcpyDeviceToHost, st));
         HIPCHK(hipEventRecord(ev_res, st));
     }
     double J_from_host(double* mis_out) {
@@ -1052,7 +1053,7 @@ class Problem : public ProblemBase {
 
     double gradient(const void* v, void* g, bool reuse) override {
         pre_g = nullptr;
-        gradient_async(v, g, reuse);
+        gradient_async(v, g, reuse, true);
         return resolve_J();
     }
 
@@ -1061,13 +1062,18 @@ class Problem : public ProblemBase {
     // up.  The solver calls this where J is already known (the accepted trial's
     // forward solve is reused) or is needed only at the end of the step.
     bool J_pending = false;
+    bool J_event = false;  // an event follows the mismatch (else: wait for the stream)
     double resolve_J() {
         if (!J_pending) return 0.0;
-        event_sync(ev_res);
+        if (J_event) event_sync(ev_res);
+        else stream_sync(st);
         J_pending = false;
         return J_from_host(nullptr);
     }
-    void gradient_async(const void* v, void* g, bool reuse) {
+    // J_event: record an event behind the mismatch, so that resolve_J waits
+    // for it alone (an event in the stream costs the device a short pause;
+    // the solver, which takes J up after a later synchronisation, records none)
+    void gradient_async(const void* v, void* g, bool reuse, bool J_event_ = false) {
         if (reuse) {
             if (!fwd_valid || fwd_v != v)
                 throw Error(GANMRES_ESTATE, "reuse_forward without a kept forward solve for this v");
@@ -1080,7 +1086,8 @@ class Problem : public ProblemBase {
         }
         mismatch(true);
         // J reaches the host while the adjoint and the assembly run
-        J_to_host();
+        J_event = J_event_;
+        if (J_event) J_to_host();
         backward();
         // assembly g = alpha L v + [P] b (the operator fused with the last
         // forward and the first inverse pass)
@@ -1134,9 +1141,6 @@ class Problem : public ProblemBase {
                 return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial,
                                               dres + R_SMAX, st);
             });
-        HIPCHK(hipMemcpyAsync(hres + R_DOT, dres + R_DOT,
-                              sizeof(double) * ((keep ? R_CROSS + 2 * nb : R_SMAX + 1) - R_DOT),
-                              hipMemcpyDeviceToHost, st));
     }
     // after the stream has synchronised: the results of precond_launch
     void precond_collect(bool keep) {
@@ -1936,7 +1940,6 @@ class Problem : public ProblemBase {
                      const std::vector<double>& rho, int ngrad, ganmres_step_info* info) {
         ++k;
         run(KC_REDUCE, [&] { return launch_maxabs<T>(Gn, vseg(), partial, dres + R_MAX, st); });
-        HIPCHK(hipMemcpyAsync(hres + R_MAX, dres + R_MAX, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
         HIPCHK(hipMemcpyAsync(v, Vn, sizeof(T) * d * N, hipMemcpyDeviceToDevice, st));
         // the next iteration starts with the direction of g^{k+1}: launched
         // now, it reaches the host with this synchronisation
@@ -1947,7 +1950,7 @@ class Problem : public ProblemBase {
             precond_collect(true);
             pre_g = Gn;
         }
-        if (J_pending) resolve_J();  // the copy behind ev_res has run
+        if (J_pending) resolve_J();  // the stream has passed the mismatch
         const std::vector<double>& Jv = Jnew.empty() ? J_s : Jnew;
         const std::vector<double> ginf(hres + R_MAX, hres + R_MAX + nb);
         bool finite = true;

@@ -24,6 +24,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# the fraction of the HBM peak the transport kernels are asked to reach
+TARGET_FRAC = 0.6
 
 
 def log(*a):
@@ -126,10 +128,12 @@ def rel_errors(a32, a64):
 def roofline_obj(kernel, bytes_per_launch, ms, count, traffic=None):
     avg_ms = ms / count
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    frac = achieved / HBM_PEAK_GBS
     return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "unit": "GB/s", "frac": round(frac, 4), "traffic": traffic,
             "avg_launch_us": round(avg_ms * 1e3, 2), "bytes_per_launch": int(bytes_per_launch),
-            "launches": count}
+            "launches": count, "target_frac": TARGET_FRAC,
+            "shortfall": round(max(0.0, TARGET_FRAC - frac), 4)}
 
 
 def algorithmic_bytes(kernel, wl, N, s):

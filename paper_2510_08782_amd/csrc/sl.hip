@@ -777,6 +777,20 @@ struct CharacteristicsBody {
         }
         const Window win = tile_window<C>(fmn, fmx, red);
         if (win.lds != LDS) return;
+        // the stencils of the predictor points (weights, first tap) serve every
+        // component: computed once, before the first staging
+        Stencil<T> stx[C::PTS], sty[C::PTS];
+        if constexpr (LDS) {
+    #pragma unroll
+            for (int k = 0; k < C::PTS; ++k) {
+                int lx, ly, lz;
+                pm.local(k, lx, ly, lz);
+                const T e0 = DIM == 3 ? u[k][0] : T(0), e1 = DIM == 3 ? u[k][1] : u[k][0];
+                const T e2 = DIM == 3 ? u[k][2] : u[k][1];
+                if (DOX) stx[k] = lds_stencil<C>(win, lx, ly, lz, -e0, -e1, -e2);
+                if (DOY) sty[k] = lds_stencil<C>(win, lx, ly, lz, e0, e1, e2);
+            }
+        }
     #pragma unroll
         for (int c = 0; c < DIM; ++c) {
             const T* vc = v + c * N;
@@ -794,12 +808,12 @@ struct CharacteristicsBody {
                 const T e0 = DIM == 3 ? u[k][0] : T(0), e1 = DIM == 3 ? u[k][1] : u[k][0];
                 const T e2 = DIM == 3 ? u[k][2] : u[k][1];
                 if (DOX) {
-                    const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, -e0, -e1, -e2)
+                    const T iv = LDS ? lds_interp<C>(lds, stx[k])
                                      : gather_global<T, DIM>(dm, vc, i0, i1, i2, -e0, -e1, -e2);
                     dX[c * N + lin] = T(-0.5) * (u[k][c] + s[c] * iv);
                 }
                 if (DOY) {
-                    const T iv = LDS ? gather_lds<C>(lds, win, lx, ly, lz, e0, e1, e2)
+                    const T iv = LDS ? lds_interp<C>(lds, sty[k])
                                      : gather_global<T, DIM>(dm, vc, i0, i1, i2, e0, e1, e2);
                     dY[c * N + lin] = T(0.5) * (u[k][c] + s[c] * iv);
                 }

@@ -64,9 +64,15 @@ __host__ __device__ inline long long pencil_count(const Dims& dm, int axis, int 
     return axis == 2 ? (long long)dm.n[0] * dm.n[1]
                      : (axis == 1 ? (long long)dm.n[0] * w : (long long)dm.n[1] * w);
 }
+// (pencil counts are below 2^31: the division is done in 32 bits, which costs
+// a tenth of the 64-bit sequence)
 __device__ inline long long pencil_base(const Dims& dm, int axis, int w, long long p) {
     if (axis == 2) return p * w;
-    if (axis == 1) return (p / w) * dm.n[1] * w + p % w;
+    if (axis == 1) {
+        const unsigned up = static_cast<unsigned>(p), uw = static_cast<unsigned>(w);
+        const unsigned q = up / uw;
+        return (long long)q * dm.n[1] * w + (up - q * uw);
+    }
     return p;
 }
 __device__ inline long long pencil_stride(const Dims& dm, int axis, int w) {

@@ -136,9 +136,13 @@ constexpr RadixPlanCT radix_plan_ct(int L) {
 
 // Stockham butterfly with the transform length L and the stage's sub-length
 // NS known at compile time: every division and modulus by them is constant.
-template <typename T, int R, int L, int NS>
+// DERIV (last stage of a forward transform only): each output, at its final
+// position i of the pencil, is multiplied by i k_i / L before it is stored
+// (k_i the wavenumber with the Nyquist entry zero), so that a derivative needs
+// no pass of its own over the spectrum.
+template <typename T, int R, int L, int NS, bool DERIV = false>
 __device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t, int pcshift,
-                                             const C2<T>* tw, int dir) {
+                                             const C2<T>* tw, int dir, T inv_l = T(0)) {
     const int PC = 1 << pcshift;
     const int p = t & (PC - 1);
     const int j = t >> pcshift;
@@ -158,6 +162,10 @@ __device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t,
     }
     dft_small<T, R>(a, dir);
     const int base = (j / NS) * NS * R + k;
+    if constexpr (DERIV) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) a[r] = cmuli(a[r], T(wavenumber_odd(base + r * NS, L)) * inv_l);
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) out[lpad(((base + r * NS) << pcshift) + p)] = a[r];
 }
@@ -165,8 +173,11 @@ __device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t,
 #if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
 // block_fft for a compile-time length L (NT threads per block): the radix
 // sequence, the stage lengths and the twiddle strides are constants.
-template <typename T, int L, int NT, int S = 0, int NS = 1>
-__device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int pcshift, int dir) {
+// DERIV: the last stage applies the derivative factor (see
+// stockham_butterfly_ct; forward transforms, dir = -1).
+template <typename T, int L, int NT, int S = 0, int NS = 1, bool DERIV = false>
+__device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int pcshift, int dir,
+                                      T inv_l = T(0)) {
     constexpr RadixPlanCT P = radix_plan_ct(L);
     if constexpr (S == P.n) {
         return a;
@@ -174,9 +185,9 @@ __device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int p
         constexpr int R = P.r[S];
         const int nbt = (L / R) << pcshift;
         for (int t = threadIdx.x; t < nbt; t += NT)
-            stockham_butterfly_ct<T, R, L, NS>(a, b, t, pcshift, tw, dir);
+            stockham_butterfly_ct<T, R, L, NS, DERIV && S + 1 == P.n>(a, b, t, pcshift, tw, dir, inv_l);
         __syncthreads();
-        return block_fft_ct<T, L, NT, S + 1, NS * R>(b, a, tw, pcshift, dir);
+        return block_fft_ct<T, L, NT, S + 1, NS * R, DERIV>(b, a, tw, pcshift, dir, inv_l);
     }
 }
 

@@ -224,12 +224,18 @@ struct DerivAxisBody {
                 if (G) gv[e] = ok[e] ? G[off[e]] : T(0);
                 if (more) fv[e] = ok[e] ? Fn[off[e]] : T(0);
             }
-            C2<T>* X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
-            for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
-                const int i = q >> a.pcshift;
-                X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
+            C2<T>* X;
+            if constexpr (LC > 0) {
+                // the derivative factor is applied by the last forward stage
+                X = block_fft_ct<T, LC, kFftThreads, 0, 1, true>(bufA, bufB, tw, a.pcshift, -1, inv_l);
+            } else {
+                X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
+                for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
+                    const int i = q >> a.pcshift;
+                    X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
+                }
+                __syncthreads();
             }
-            __syncthreads();
             const C2<T>* Y = tile_fft<T, LC>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
             const T* yflat = reinterpret_cast<const T*>(Y);
             const T wt = T(a.w[t]);

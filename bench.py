@@ -488,7 +488,8 @@ def main():
         extra["fp64_grad_evals_per_s"] = round(ng64 / dt64, 2)
         ms64, c64 = rep64["sl_step"]
         if c64:
-            roofline_fp64 = roofline_obj("sl_step", algorithmic_bytes("sl_step", wl, N, 8), ms64, c64)
+            roofline_fp64 = roofline_obj("sl_step", algorithmic_bytes("sl_step", wl, N, 8), ms64, c64,
+                                         measured_traffic("sl_step", "c2_128cubed_fp64"))
         extra["grad_eval_only_fp64_per_s"] = round(
             1.0 / time_gradients(torch, P64, (0.5 * vstar64).contiguous(), 5), 2)
         if not args.no_tts:

@@ -30,6 +30,10 @@ namespace {
 
 constexpr int kFftThreads = 256;
 constexpr int kItems = 8;           // tile elements per thread (tile <= 2048 elements)
+// Threads of the body-force derivative kernel: its tile of kItems reals per
+// thread then spans 128 contiguous bytes of real pencils along the strided
+// axes for lengths up to 128, and 64 up to 256 (with 256 threads: 64 and 32).
+constexpr int kDerivThreads = 512;
 constexpr int kMaxTime = 65;
 constexpr int kLdsBudget = 64 * 1024;
 constexpr int kTilesPerBlock = 2;  // grid-strided transforms: tiles per workgroup
@@ -41,10 +45,11 @@ constexpr int kTilesPerBlock = 2;  // grid-strided transforms: tiles per workgro
 size_t fft_lds_bytes(int PC, int L, int bytes_per_complex) {
     return (size_t)(2 * lpad_size(PC * L) + L) * bytes_per_complex;
 }
-int pc_shift_real(int L, int bytes_per_complex, long long npencils) {
+int pc_shift_real(int L, int bytes_per_complex, long long npencils, int threads = kFftThreads) {
     int s = 0;
-    while ((2 << (s + 1)) * L <= kFftThreads * kItems && (2LL << s) < npencils &&
-           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= kLdsBudget && s < 5)
+    while ((2 << (s + 1)) * L <= threads * kItems && (2LL << s) < npencils &&
+           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= kLdsBudget &&
+           s < (threads > kFftThreads ? 6 : 5))
         ++s;
     return s;
 }
@@ -79,19 +84,19 @@ __device__ inline long long pencil_stride(const Dims& dm, int axis, int w) {
     return axis == 2 ? 1 : (axis == 1 ? w : (long long)dm.n[1] * w);
 }
 
-template <typename T>
+template <typename T, int NT = kFftThreads>
 __device__ inline C2<T>* twiddles_to_lds(const FftPlan<T>& pl, C2<T>* tws) {
-    for (int m = threadIdx.x; m < pl.L; m += kFftThreads) tws[m] = pl.tw[m];
+    for (int m = threadIdx.x; m < pl.L; m += NT) tws[m] = pl.tw[m];
     return tws;
 }
 
 // Transform of the tile: compiled for length LC when LC > 0, else driven by
 // the runtime plan.
-template <typename T, int LC>
+template <typename T, int LC, int NT = kFftThreads>
 __device__ inline C2<T>* tile_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, const C2<T>* tw,
                                   int pcshift, int dir) {
     if constexpr (LC > 0)
-        return block_fft_ct<T, LC, kFftThreads>(a, b, tw, pcshift, dir);
+        return block_fft_ct<T, LC, NT>(a, b, tw, pcshift, dir);
     else
         return block_fft<T>(a, b, pl, tw, pcshift, dir);
 }
@@ -171,7 +176,7 @@ constexpr int kGroupTime = 9;
 // that they complete while the LDS passes run.
 template <typename T, int LC, int MT>
 struct DerivAxisBody {
-    static constexpr int kBlock = kFftThreads;
+    static constexpr int kBlock = kDerivThreads;
     using Args = DerivArgs<T, MT>;
     __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
         const DerivArgs<T, MT>& a = args_;
@@ -181,7 +186,7 @@ struct DerivAxisBody {
         C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
         C2<T>* bufB = bufA + lpad_size(PC * L);
         const FftPlan<T>& pl = a.pl;
-        const C2<T>* tw = twiddles_to_lds(a.pl, bufB + lpad_size(PC * L));
+        const C2<T>* tw = twiddles_to_lds<T, kDerivThreads>(a.pl, bufB + lpad_size(PC * L));
         const Dims& dm = a.dm;
         const long long npen = pencil_count(dm, a.axis, dm.n[2]);
         const long long stride = pencil_stride(dm, a.axis, dm.n[2]);
@@ -195,7 +200,7 @@ struct DerivAxisBody {
         T acc[kItems], fv[kItems], gv[kItems];
     #pragma unroll
         for (int e = 0; e < kItems; ++e) {
-            const int q = threadIdx.x + e * kFftThreads;
+            const int q = threadIdx.x + e * kDerivThreads;
             slot[e] = -1;
             ok[e] = false;
             off[e] = 0;
@@ -227,16 +232,16 @@ struct DerivAxisBody {
             C2<T>* X;
             if constexpr (LC > 0) {
                 // the derivative factor is applied by the last forward stage
-                X = block_fft_ct<T, LC, kFftThreads, 0, 1, true>(bufA, bufB, tw, a.pcshift, -1, inv_l);
+                X = block_fft_ct<T, LC, kDerivThreads, 0, 1, true>(bufA, bufB, tw, a.pcshift, -1, inv_l);
             } else {
-                X = tile_fft<T, LC>(bufA, bufB, pl, tw, a.pcshift, -1);
-                for (int q = threadIdx.x; q < PC * L; q += kFftThreads) {
+                X = tile_fft<T, LC, kDerivThreads>(bufA, bufB, pl, tw, a.pcshift, -1);
+                for (int q = threadIdx.x; q < PC * L; q += kDerivThreads) {
                     const int i = q >> a.pcshift;
                     X[lpad(q)] = cmuli(X[lpad(q)], T(wavenumber_odd(i, L)) * inv_l);
                 }
                 __syncthreads();
             }
-            const C2<T>* Y = tile_fft<T, LC>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
+            const C2<T>* Y = tile_fft<T, LC, kDerivThreads>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
             const T* yflat = reinterpret_cast<const T*>(Y);
             const T wt = T(a.w[t]);
     #pragma unroll
@@ -833,7 +838,7 @@ struct C2cSpecBody {
 // its plan and dispatched to the body compiled for it.
 template <typename T, int MT>
 struct DerivAxisAnyBody {
-    static constexpr int kBlock = kFftThreads;
+    static constexpr int kBlock = kDerivThreads;
     using Args = DerivArgs<T, MT>;
     __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
         with_length_dev(a.pl.L, [&](auto lc) __attribute__((always_inline)) { DerivAxisBody<T, decltype(lc)::value, MT>::run(a, bk); });
@@ -1155,7 +1160,8 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
         a.dm = dm;
         a.pl = pl.p[axis];
         a.axis = axis;
-        a.pcshift = pc_shift_real(dm.n[axis], (int)sizeof(C2<T>), pencil_count(dm, axis, dm.n[2]));
+        a.pcshift = pc_shift_real(dm.n[axis], (int)sizeof(C2<T>), pencil_count(dm, axis, dm.n[2]),
+                                  kDerivThreads);
         a.ntime = ntime;
         a.accumulate = accumulate;
         a.has_g = G != nullptr;
@@ -1168,7 +1174,7 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     };
     const int L = dm.n[axis];
     const long long npen = pencil_count(dm, axis, dm.n[2]);
-    const int PC = 1 << pc_shift_real(L, (int)sizeof(C2<T>), npen);
+    const int PC = 1 << pc_shift_real(L, (int)sizeof(C2<T>), npen, kDerivThreads);
     const long long tiles = (npen + 2 * PC - 1) / (2 * PC);
     const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
     if (ntime <= kGroupTime) {

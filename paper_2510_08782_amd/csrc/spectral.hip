@@ -34,6 +34,16 @@ constexpr int kItems = 8;           // tile elements per thread (tile <= 2048 el
 // thread then spans 128 contiguous bytes of real pencils along the strided
 // axes for lengths up to 128, and 64 up to 256 (with 256 threads: 64 and 32).
 constexpr int kDerivThreads = 512;
+// Complex axis passes of length >= kWideLength run 512-thread tiles (up to
+// 80 KB of LDS), so that along the strided axes a tile spans 128 (256, 192)
+// or 64 (384, 512) contiguous bytes instead of half that; shorter lengths keep
+// 256 threads (their tiles already span 128 bytes).  The fused spectral pass
+// keeps 256 threads at every length (its tiles hold every component: wider
+// ones were slower).
+constexpr int kWideLength = 192;
+constexpr int kWideThreads = 512;
+constexpr size_t kWideLds = 80 * 1024;
+inline int c2c_threads(int L) { return L >= kWideLength ? kWideThreads : kFftThreads; }
 constexpr int kMaxTime = 65;
 constexpr int kLdsBudget = 64 * 1024;
 constexpr int kTilesPerBlock = 2;  // grid-strided transforms: tiles per workgroup
@@ -54,10 +64,11 @@ int pc_shift_real(int L, int bytes_per_complex, long long npencils, int threads 
     return s;
 }
 // Same for in-place complex transforms: tiles of PC complex pencils.
-int pc_shift_cplx(int L, int bytes_per_complex, long long npencils) {
+int pc_shift_cplx(int L, int bytes_per_complex, long long npencils, int threads = kFftThreads) {
+    const size_t budget = threads > kFftThreads ? kWideLds : kLdsBudget;
     int s = 0;
-    while ((1 << (s + 1)) * L <= kFftThreads * kItems && (1LL << s) < npencils &&
-           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= kLdsBudget && s < 5)
+    while ((1 << (s + 1)) * L <= threads * kItems && (1LL << s) < npencils &&
+           fft_lds_bytes(1 << (s + 1), L, bytes_per_complex) <= budget && s < 5)
         ++s;
     return s;
 }
@@ -378,9 +389,9 @@ struct C2cAxisArgs {
     int dir;
     SpecPtrs<T> sp;
 };
-template <typename T, int LC>
+template <typename T, int LC, int NT = kFftThreads>
 struct C2cAxisBody {
-    static constexpr int kBlock = kFftThreads;
+    static constexpr int kBlock = NT;
     using Args = C2cAxisArgs<T>;
     __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
         const Dims& dm = args_.dm;
@@ -394,7 +405,7 @@ struct C2cAxisBody {
         C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
         C2<T>* bufB = bufA + lpad_size(PC * L);
         const FftPlan<T>& pl = pl0;
-        const C2<T>* tw = twiddles_to_lds(pl0, bufB + lpad_size(PC * L));
+        const C2<T>* tw = twiddles_to_lds<T, NT>(pl0, bufB + lpad_size(PC * L));
         C2<T>* spec = sp.spec[bk.y];
         const int nh = dm.n2h;
         const long long npen = pencil_count(dm, axis, nh);
@@ -410,7 +421,7 @@ struct C2cAxisBody {
             base = ok ? pencil_base(dm, axis, nh, p) : 0;
     #pragma unroll
             for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
+                const int q = threadIdx.x + e * NT;
                 vals[e] = (q < nitems && ok) ? spec[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
             }
         };
@@ -423,7 +434,7 @@ struct C2cAxisBody {
         for (;;) {
     #pragma unroll
             for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
+                const int q = threadIdx.x + e * NT;
                 if (q < nitems) bufA[lpad(q)] = vals[e];
             }
             __syncthreads();
@@ -431,10 +442,10 @@ struct C2cAxisBody {
             long long nbase = 0;
             bool nok = false;
             if (next < ntiles) load(next, vals, nbase, nok);
-            const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, dir);
+            const C2<T>* Z = tile_fft<T, LC, NT>(bufA, bufB, pl, tw, pcshift, dir);
     #pragma unroll
             for (int e = 0; e < kItems; ++e) {
-                const int q = threadIdx.x + e * kFftThreads;
+                const int q = threadIdx.x + e * NT;
                 if (q < nitems && ok) spec[base + (q >> pcshift) * stride] = Z[lpad(q)];
             }
             if (next >= ntiles) break;
@@ -852,12 +863,12 @@ struct R2cRowsAnyBody {
         with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { R2cRowsBody<TI, TC, decltype(lc)::value>::run(a, bk); });
     }
 };
-template <typename T>
+template <typename T, int NT = kFftThreads>
 struct C2cAxisAnyBody {
-    static constexpr int kBlock = kFftThreads;
+    static constexpr int kBlock = NT;
     using Args = C2cAxisArgs<T>;
     __device__ __forceinline__ static void run(const Args& a, const Blk& bk) {
-        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { C2cAxisBody<T, decltype(lc)::value>::run(a, bk); });
+        with_length_dev(a.pl0.L, [&](auto lc) __attribute__((always_inline)) { C2cAxisBody<T, decltype(lc)::value, NT>::run(a, bk); });
     }
 };
 template <typename T>
@@ -1222,13 +1233,21 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
     for (int axis = 1; axis >= 3 - dm.dim + (skip_last ? 1 : 0); --axis) {
         const int L = dm.n[axis];
         const long long npen = pencil_count(dm, axis, dm.n2h);
-        const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen);
+        const int nt = c2c_threads(L);
+        const int sh = pc_shift_cplx(L, (int)sizeof(C2<TC>), npen, nt);
         const int PC = 1 << sh;
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
+        const C2cAxisArgs<TC> ca{dm, pl.p[axis], axis, sh, -1, sp};
+        const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<TC>));
         with_length(L, [&](auto lc) {
-            submit<C2cAxisBody<TC, decltype(lc)::value>,
-                   MergeFamily<decltype(lc)::value, C2cAxisBody<TC, decltype(lc)::value>, C2cAxisAnyBody<TC>>>(
-                g, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st, C2cAxisArgs<TC>{dm, pl.p[axis], axis, sh, -1, sp});
+            constexpr int LC = decltype(lc)::value;
+            if (nt == kWideThreads)
+                submit<C2cAxisBody<TC, LC, kWideThreads>,
+                       MergeFamily<LC, C2cAxisBody<TC, LC, kWideThreads>, C2cAxisAnyBody<TC, kWideThreads>>>(
+                    g, lds, st, ca);
+            else
+                submit<C2cAxisBody<TC, LC>, MergeFamily<LC, C2cAxisBody<TC, LC>, C2cAxisAnyBody<TC>>>(
+                    g, lds, st, ca);
         });
     }
     return hipGetLastError();
@@ -1249,13 +1268,21 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
     for (int axis = 3 - dm.dim + (skip_first ? 1 : 0); axis <= 1; ++axis) {
         const int L = dm.n[axis];
         const long long npen = pencil_count(dm, axis, dm.n2h);
-        const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen);
+        const int nt = c2c_threads(L);
+        const int sh = pc_shift_cplx(L, (int)sizeof(C2<T>), npen, nt);
         const int PC = 1 << sh;
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
+        const C2cAxisArgs<T> ca{dm, pl.p[axis], axis, sh, +1, sp};
+        const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
         with_length(L, [&](auto lc) {
-            submit<C2cAxisBody<T, decltype(lc)::value>,
-                   MergeFamily<decltype(lc)::value, C2cAxisBody<T, decltype(lc)::value>, C2cAxisAnyBody<T>>>(
-                g, fft_lds_bytes(PC, L, sizeof(C2<T>)), st, C2cAxisArgs<T>{dm, pl.p[axis], axis, sh, +1, sp});
+            constexpr int LC = decltype(lc)::value;
+            if (nt == kWideThreads)
+                submit<C2cAxisBody<T, LC, kWideThreads>,
+                       MergeFamily<LC, C2cAxisBody<T, LC, kWideThreads>, C2cAxisAnyBody<T, kWideThreads>>>(
+                    g, lds, st, ca);
+            else
+                submit<C2cAxisBody<T, LC>, MergeFamily<LC, C2cAxisBody<T, LC>, C2cAxisAnyBody<T>>>(
+                    g, lds, st, ca);
         });
     }
     {

@@ -85,6 +85,11 @@ CASES = [
     # a 256-long leading axis: the transforms compiled for that length along
     # the slowest axis, and many z tiles of the gather
     ("c2", (256, 24, 32), 2),
+    # lengths from 192 up run the 512-thread complex passes: 192 compiled along
+    # the slowest axis, 216 (= 2^3 3^3) on the runtime plan along the strided
+    # 2-D axis
+    ("c2", (192, 16, 24), 2),
+    ("c0", (216, 48), 3),
 ]
 
 

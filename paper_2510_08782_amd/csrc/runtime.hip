@@ -505,6 +505,7 @@ class Problem : public ProblemBase {
     // timing events
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pool;
     std::vector<int> ev_kind;
+    std::vector<int> ev_count;  // launches inside each bracketed interval
     size_t ev_used = 0;
 
     T* alloc_T(long long n) {
@@ -745,13 +746,15 @@ class Problem : public ProblemBase {
             HIPCHK(hipEventCreateWithFlags(&b2, hipEventDisableSystemFence));
             ev_pool.push_back({a, b2});
             ev_kind.push_back(kind);
+            ev_count.push_back(1);
         }
         ev_kind[ev_used] = kind;
         HIPCHK(hipEventRecord(ev_pool[ev_used].first, st));
     }
-    void tend() {
+    void tend(int launches = 1) {
         if (!tcur) return;
         tcur = false;
+        ev_count[ev_used] = launches;
         HIPCHK(hipEventRecord(ev_pool[ev_used].second, st));
         ++ev_used;
         if (ev_used >= 4096) timing_flush();
@@ -763,7 +766,7 @@ class Problem : public ProblemBase {
             float ms = 0.f;
             HIPCHK(hipEventElapsedTime(&ms, ev_pool[i].first, ev_pool[i].second));
             tms[ev_kind[i]] += ms;
-            tcount[ev_kind[i]] += 1;
+            tcount[ev_kind[i]] += ev_count[i];
         }
         ev_used = 0;
     }
@@ -773,6 +776,16 @@ class Problem : public ProblemBase {
         tbegin(kind);
         HIPCHK(f());
         tend();
+    }
+    // n launches of one class back to back (f(i) enqueues the i-th and nothing
+    // else): one pair of timing events brackets them all, since every event in
+    // the stream pauses the device briefly
+    template <typename F>
+    void run_seq(int kind, int n, F&& f) {
+        if (n <= 0) return;
+        tbegin(kind);
+        for (int i = 0; i < n; ++i) HIPCHK(f(i));
+        tend(n);
     }
 
     // result slots [at, at + n) on the host (synchronises).  Every slot is
@@ -908,10 +921,9 @@ class Problem : public ProblemBase {
     }
 
     void forward() {
-        for (int j = 0; j < cfg.nt; ++j)
-            run(KC_SL, [&] {
-                return launch_sl_step<T>(dm, mstate(j), dX, cfac, dbound, mstate(j + 1), st, tabX, tw(tabX_ok));
-            });
+        run_seq(KC_SL, cfg.nt, [&](int j) {
+            return launch_sl_step<T>(dm, mstate(j), dX, cfac, dbound, mstate(j + 1), st, tabX, tw(tabX_ok));
+        });
     }
 
     // mismatch sums per problem -> dres[R_MIS..]; optionally lam^nt = m1 - m^nt
@@ -993,11 +1005,11 @@ class Problem : public ProblemBase {
     void backward() {
         const int nt = cfg.nt;
         if (full) {
-            for (int j = nt - 1; j >= 0; --j)
-                run(KC_SL, [&] {
-                    return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
-                                             lamh + (long long)j * N, st, tabY, tw(tabY_ok));
-                });
+            run_seq(KC_SL, nt, [&](int i) {
+                const int j = nt - 1 - i;
+                return launch_sl_step<T>(dm, lamh + (long long)(j + 1) * N, dY, bfac, dbound,
+                                         lamh + (long long)j * N, st, tabY, tw(tabY_ok));
+            });
             std::vector<const T*> mp(nt + 1), lp(nt + 1);
             std::vector<double> w(nt + 1);
             for (int t = 0; t <= nt; ++t) {
@@ -1017,12 +1029,11 @@ class Problem : public ProblemBase {
             std::vector<T*> mp(len + 1), lp(len + 1);
             mp[0] = ck[sgi];
             mp[len] = ck[sgi + 1];
-            for (int i = 1; i < len; ++i) {
-                mp[i] = mint[i - 1];
-                T* src = mp[i - 1];
-                T* dst = mp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dX, cfac, dbound, dst, st, tabX, tw(tabX_ok)); });
-            }
+            for (int i = 1; i < len; ++i) mp[i] = mint[i - 1];
+            run_seq(KC_SL, len - 1, [&](int q) {
+                const int i = q + 1;
+                return launch_sl_step<T>(dm, mp[i - 1], dX, cfac, dbound, mp[i], st, tabX, tw(tabX_ok));
+            });
             std::vector<int> idx;
             for (int i = 0; i < (int)lpool.size(); ++i)
                 if (i != top) idx.push_back(i);
@@ -1031,10 +1042,11 @@ class Problem : public ProblemBase {
             for (int i = len - 1, q = 0; i >= 0; --i, ++q) {
                 lp[i] = lpool[idx[q]];
                 if (i == 0) newtop = idx[q];
-                T* src = lp[i + 1];
-                T* dst = lp[i];
-                run(KC_SL, [&] { return launch_sl_step<T>(dm, src, dY, bfac, dbound, dst, st, tabY, tw(tabY_ok)); });
             }
+            run_seq(KC_SL, len, [&](int q) {
+                const int i = len - 1 - q;
+                return launch_sl_step<T>(dm, lp[i + 1], dY, bfac, dbound, lp[i], st, tabY, tw(tabY_ok));
+            });
             // time level j0 belongs to the previous segment, except t = 0
             const int i0 = sgi == 0 ? 0 : 1;
             std::vector<const T*> fm, fl;

@@ -348,7 +348,9 @@ int ganmres_get_field(ganmres_handle* h, int which, int j, void* out);
  * selected kernel classes (all by default) with HIP events on its stream and
  * accumulates per-class device time.  ganmres_timing_select sets the classes
  * (bit k of mask: class k); an event pair costs the stream a few microseconds,
- * so a measurement that times one class should select only that one.
+ * so a measurement that times one class should select only that one.  The
+ * gathers of one forward or adjoint sweep run back to back and share one
+ * event pair: they add their number of launches and the time of the sweep.
  * ganmres_timing_get returns the accumulated milliseconds and launch count of
  * class `kernel` (see ganmres_kernel_name) and the number of classes;
  * ganmres_timing_reset clears the accumulators. */

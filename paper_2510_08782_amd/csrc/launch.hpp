@@ -154,11 +154,14 @@ hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* co
 //   kSpecGrad:    io = alpha l_p vh + P io      (as launch_spec_gradient)
 //   kSpecPrecond: io = -P io / (alpha lbar_p)   (as launch_spec_precond; keep
 //                 nullable receives a copy of the spectrum)
+// kSpecGrad with keep and pre (both or neither): the preconditioned direction
+// of the new gradient, -P g^ / (alpha lbar_p) over the full spectrum, goes to
+// keep[c] and pre[c] (the caller transforms pre back; keep stays)
 constexpr int kSpecGrad = 0, kSpecPrecond = 1;
 template <typename T>
 hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
                              const SpecOpParams& sp, C2<T>* const* io, C2<double>* const* vh,
-                             C2<T>* const* keep, hipStream_t st);
+                             C2<T>* const* keep, hipStream_t st, C2<T>* const* pre = nullptr);
 // sh[c] = sign (alpha lbar_p)^expo P gh[c] (P only when sp.leray; lbar_p: l_p
 // with its zero entry set to one); band_cut: the modes outside |k_i| <= n_i/2 - 1
 // are set to zero.

@@ -461,6 +461,11 @@ class Problem : public ProblemBase {
     C2<double>* vh[3];
     CT* wh[3];
     CT* sk[3];                   // spectrum of the last search direction (line search)
+    // The solver's gradients also yield the next direction's spectrum (in sk,
+    // and a copy in ws that its inverse transform consumes): pre_spec_g is
+    // the gradient it belongs to, nullptr when none is pending.
+    CT* ws[3] = {nullptr, nullptr, nullptr};
+    const void* pre_spec_g = nullptr;
     const void* vh_of = nullptr;  // velocity whose spectrum vh holds
     bool reg_from_device = true;  // R(v) of the next finish_J comes from the device sums
     double *partial, *dres;
@@ -974,6 +979,7 @@ class Problem : public ProblemBase {
 
     double objective(const void* v, bool keep, double* mis) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         prepare(v, false);
         forward();
         mismatch(false);
@@ -1065,6 +1071,7 @@ class Problem : public ProblemBase {
 
     double gradient(const void* v, void* g, bool reuse) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         gradient_async(v, g, reuse, true);
         return resolve_J();
     }
@@ -1085,7 +1092,10 @@ class Problem : public ProblemBase {
     // J_event: record an event behind the mismatch, so that resolve_J waits
     // for it alone (an event in the stream costs the device a short pause;
     // the solver, which takes J up after a later synchronisation, records none)
-    void gradient_async(const void* v, void* g, bool reuse, bool J_event_ = false) {
+    // want_pre: the assembly also leaves the spectrum of the preconditioned
+    // direction of g (for the precond_launch of the same g that follows)
+    void gradient_async(const void* v, void* g, bool reuse, bool J_event_ = false,
+                        bool want_pre = false) {
         if (reuse) {
             if (!fwd_valid || fwd_v != v)
                 throw Error(GANMRES_ESTATE, "reuse_forward without a kept forward solve for this v");
@@ -1105,10 +1115,13 @@ class Problem : public ProblemBase {
         // forward and the first inverse pass)
         const T* bin[3] = {comp(b, 0), comp(b, 1), d == 3 ? comp(b, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, bin, wh, d, st, 1); });
+        if (want_pre && !ws[0])
+            for (int cc = 0; cc < d; ++cc) ws[cc] = alloc_C(NH);
         run(KC_SPEC, [&] {
             return launch_spec_fused<T>(dm, plans, kSpecGrad, specop(cfg.incompressible != 0), wh, vh,
-                                        nullptr, st);
+                                        want_pre ? sk : nullptr, st, want_pre ? ws : nullptr);
         });
+        pre_spec_g = want_pre ? g : nullptr;
         T* gout[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, gout, nullptr, 1.0 / Nt, d, st, 1); });
         J_pending = true;
@@ -1116,6 +1129,7 @@ class Problem : public ProblemBase {
 
     double precond(const void* g, void* s) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         precond_keep(g, s, false);
         double t = 0.0;
         for (int i = 0; i < nb; ++i) t += gs_s[i];
@@ -1132,6 +1146,26 @@ class Problem : public ProblemBase {
     }
     // the launches of precond_keep and the copy of its results to the host
     void precond_launch(const void* g, void* s, bool keep) {
+        T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
+        if (keep && pre_spec_g == g) {
+            // the direction's spectrum came with the gradient's assembly: only
+            // its inverse transform and the scalars remain
+            pre_spec_g = nullptr;
+            run(KC_REDUCE, [&] {
+                return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
+            });
+            run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, ws, sout, nullptr, 1.0 / Nt, d, st, 0); });
+            run(KC_REDUCE, [&] {
+                return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), vseg(), partial,
+                                     dres + R_DOT, st);
+            });
+            run(KC_REDUCE, [&] {
+                return launch_velocity_max<T>(dm, static_cast<const T*>(s), cscale, partial,
+                                              dres + R_SMAX, st);
+            });
+            return;
+        }
+        pre_spec_g = nullptr;
         const T* gin[3] = {comp(g, 0), comp(g, 1), d == 3 ? comp(g, 2) : nullptr};
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, gin, wh, d, st, 1); });
         run(KC_SPEC, [&] {
@@ -1142,7 +1176,6 @@ class Problem : public ProblemBase {
             run(KC_REDUCE, [&] {
                 return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
             });
-        T* sout[3] = {comp(s, 0), comp(s, 1), d == 3 ? comp(s, 2) : nullptr};
         run(KC_IRFFT, [&] { return launch_irfft<T>(dm, plans, wh, sout, nullptr, 1.0 / Nt, d, st, 1); });
         run(KC_REDUCE, [&] {
             return launch_dot<T>(static_cast<const T*>(g), static_cast<const T*>(s), vseg(), partial,
@@ -1230,6 +1263,7 @@ class Problem : public ProblemBase {
     // the caller's v may have changed since any earlier call: solve the state again
     void hessian_matvec(const void* v, const void* vt, void* out) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         check_newton_setup();
         prepare(v, true);
         forward();
@@ -1565,6 +1599,7 @@ class Problem : public ProblemBase {
 
     void newton_precond(int which, const void* v, const void* r, void* z) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         check_newton_setup();
         if (which != GANMRES_PC_IREG && which != GANMRES_PC_H0RPC && which != GANMRES_PC_2LRPCSYM)
             throw Error(GANMRES_EINVAL, "unknown preconditioner");
@@ -1653,6 +1688,7 @@ class Problem : public ProblemBase {
         const double R0 = reg_s[0], um0 = umax;
         const double gs = inner(G, S);
         const T* sin_[3] = {comp(S, 0), comp(S, 1), d == 3 ? comp(S, 2) : nullptr};
+        pre_spec_g = nullptr;
         run(KC_RFFT, [&] { return launch_rfft<T, T>(dm, plans, sin_, sk, d, st); });
         run(KC_REDUCE, [&] {
             return launch_spec_cross<T>(dm, specop(false), vh, sk, partial, dres + R_CROSS, st);
@@ -1707,6 +1743,7 @@ class Problem : public ProblemBase {
     std::vector<std::unique_ptr<DevBuf>> dfm_bufs;
     void deformation(const void* v, void* det, double* stats) override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         prepare(v, false);
         // dX now belongs to v: a kept forward history of another velocity is void
         fwd_valid = false;
@@ -1773,6 +1810,7 @@ class Problem : public ProblemBase {
     // -- GA-NGMRES ----------------------------------------------------------
     void reset() override {
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         started = false;
         hist.clear();
         k = 0;
@@ -1845,6 +1883,7 @@ class Problem : public ProblemBase {
         const double um0 = umax;
         if (pre_g != Gc) precond_keep(Gc, s, true);
         pre_g = nullptr;
+        pre_spec_g = nullptr;
         std::vector<double> cA(nb), cB(nb);
         for (int i = 0; i < nb; ++i) {
             cA[i] = cell / double(Nt) * crossA[i];
@@ -2015,8 +2054,9 @@ class Problem : public ProblemBase {
         const std::vector<double> rho = line_search(rv(cur), rg(cur), p, info, Jq);
         T* q = static_cast<T*>(qb->p);
         T* gq = static_cast<T*>(gqb->p);
-        // J(q) is the accepted trial's: no need to wait for it
-        gradient_async(q, gq, true);
+        // J(q) is the accepted trial's: no need to wait for it; in an FP step
+        // g(q) is the next iterate's gradient, whose direction comes next
+        gradient_async(q, gq, true, false, is_fp(k, p));
         J_pending = false;
         ++ngrad;
         // the free slot (not in the window)
@@ -2041,7 +2081,7 @@ class Problem : public ProblemBase {
             std::vector<const T*> xs(wk + 1);
             for (int i = 0; i <= wk; ++i) xs[i] = rv(hist[hist.size() - 1 - i]);
             combine(q, xs, beta, wk + 1, rv(slot));
-            gradient_async(rv(slot), rg(slot), false);  // J taken up in finish_step
+            gradient_async(rv(slot), rg(slot), false, false, true);  // J taken up in finish_step
             ++ngrad;
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_NGMRES;
@@ -2090,7 +2130,7 @@ class Problem : public ProblemBase {
             // v^{k+1} = q: the trial buffer becomes the next iterate, and its
             // forward solve from the line search is reused
             std::swap(ring_v[nxt], qb);
-            gradient_async(rv(nxt), rg(nxt), true);
+            gradient_async(rv(nxt), rg(nxt), true, false, true);
             J_pending = false;
             Jnew = J_s;
             for (int i = 0; i < nb; ++i) info[i].step_kind = GANMRES_STEP_FP;
@@ -2102,7 +2142,7 @@ class Problem : public ProblemBase {
             std::vector<const T*> xs(wk);
             for (int i = 1; i <= wk; ++i) xs[i - 1] = aq(hist[hist.size() - i]);
             combine(q, xs, xi, wk, rv(nxt));
-            gradient_async(rv(nxt), rg(nxt), false);  // J taken up in finish_step
+            gradient_async(rv(nxt), rg(nxt), false, false, true);  // J taken up in finish_step
             for (int i = 0; i < nb; ++i) {
                 info[i].step_kind = GANMRES_STEP_AA;
                 info[i].n_beta = wk;

@@ -741,6 +741,7 @@ struct C2cSpecArgs {
     SpecPtrs<double> vh;
     SpecPtrs<T> keep;
     int has_keep;
+    SpecPtrs<T> pre;  // kSpecGrad with has_keep: second copy of the direction's spectrum
 };
 template <typename T, int LC, int OP>
 struct C2cSpecBody {
@@ -756,6 +757,7 @@ struct C2cSpecBody {
         const SpecPtrs<double>& vh = args_.vh;
         const SpecPtrs<T>& keep = args_.keep;
         int has_keep = args_.has_keep;
+        const SpecPtrs<T>& pre = args_.pre;
         const int L = LC > 0 ? LC : pl0.L;
         const int PC = 1 << pcshift;
         C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
@@ -811,6 +813,25 @@ struct C2cSpecBody {
                             const C2<double> z = vh.spec[c][lin];
                             R[c][e] = cmk(T(al * z.x + double(g[c].x)), T(al * z.y + double(g[c].y)));
                         }
+                    if (has_keep) {
+                        // the next direction from this gradient's spectrum: the
+                        // preconditioner below, applied to g^ instead of to the
+                        // transform of the gradient once it is back on the grid
+                        C2<T> h[3];
+    #pragma unroll
+                        for (int c = 0; c < 3; ++c) h[c] = c < dim ? R[c][e] : cmk(T(0), T(0));
+                        if (sop.leray) leray_point(kv, dim, h);
+                        double l = ipow(kv.k2, sop.p);
+                        if (l == 0.0) l = 1.0;
+                        const T f = T(-1.0 / (seg_alpha(sop, dm, lin) * l));
+    #pragma unroll
+                        for (int c = 0; c < 3; ++c)
+                            if (c < dim) {
+                                const C2<T> sv = cscale(h[c], f);
+                                keep.spec[c][lin] = sv;
+                                pre.spec[c][lin] = sv;
+                            }
+                    }
                 } else {
                     double l = ipow(kv.k2, sop.p);
                     if (l == 0.0) l = 1.0;
@@ -1330,14 +1351,16 @@ hipError_t launch_spec_precond(const Dims& dm, const SpecOpParams& sp, C2<T>* co
 template <typename T>
 hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
                              const SpecOpParams& sp, C2<T>* const* io, C2<double>* const* vh,
-                             C2<T>* const* keep, hipStream_t st) {
+                             C2<T>* const* keep, hipStream_t st, C2<T>* const* pre) {
     if (sp.dim != dm.dim || (op != kSpecGrad && op != kSpecPrecond)) return hipErrorInvalidValue;
-    SpecPtrs<T> a{}, k{};
+    if (op == kSpecGrad && (keep == nullptr) != (pre == nullptr)) return hipErrorInvalidValue;
+    SpecPtrs<T> a{}, k{}, pr{};
     SpecPtrs<double> v{};
     for (int c = 0; c < sp.dim; ++c) {
         a.spec[c] = io[c];
         k.spec[c] = keep ? keep[c] : nullptr;
         v.spec[c] = vh ? vh[c] : nullptr;
+        pr.spec[c] = pre ? pre[c] : nullptr;
     }
     if (op == kSpecGrad && !vh) return hipErrorInvalidValue;
     const int axis = 3 - dm.dim;
@@ -1348,7 +1371,7 @@ hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
     // one tile per workgroup: a tile carries every component, so the grid is a
     // third of that of a single-field pass and needs all its workgroups
     const unsigned g = strided_blocks((npen + PC - 1) / PC, 1);
-    const C2cSpecArgs<T> ca{dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr};
+    const C2cSpecArgs<T> ca{dm, pl.p[axis], axis, sh, sp, a, v, k, keep != nullptr, pr};
     const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
     with_length(L, [&](auto lc) {
         if (op == kSpecGrad)
@@ -1452,7 +1475,8 @@ hipError_t launch_spec_regvalue(const Dims& dm, const SpecOpParams& sp, C2<T>* c
                                         int);                                                     \
     template hipError_t launch_spec_fused<T>(const Dims&, const SpectralPlans<T>&, int,           \
                                              const SpecOpParams&, C2<T>* const*,                  \
-                                             C2<double>* const*, C2<T>* const*, hipStream_t);     \
+                                             C2<double>* const*, C2<T>* const*, hipStream_t,      \
+                                             C2<T>* const*);                                      \
     template hipError_t launch_spec_gradient<T>(const Dims&, const SpecOpParams&,                 \
                                                 C2<double>* const*, C2<T>* const*, C2<T>* const*, \
                                                 hipStream_t);                                     \

@@ -140,9 +140,55 @@ constexpr RadixPlanCT radix_plan_ct(int L) {
 // position i of the pencil, is multiplied by i k_i / L before it is stored
 // (k_i the wavenumber with the Nyquist entry zero), so that a derivative needs
 // no pass of its own over the spectrum.
-template <typename T, int R, int L, int NS, bool DERIV = false>
+// PCS >= 0: the tile's log2 pencil count is this constant (pcshift is then
+// ignored).  lpad(c + 16 m) = lpad(c) + 17 m, so where the element stride
+// between the R inputs (outputs) of a butterfly, in slots of the interleaved
+// tile, is a multiple of 16, their LDS slots are one base plus constant
+// offsets: one address per butterfly instead of one per element.
+template <typename T, int R, int L, int NS, bool DERIV = false, int PCS = -1>
 __device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t, int pcshift,
                                              const C2<T>* tw, int dir, T inv_l = T(0)) {
+    if constexpr (PCS >= 0) {
+        constexpr int PC = 1 << PCS;
+        constexpr int nb = L / R;
+        const int p = t & (PC - 1);
+        const int j = t >> PCS;
+        const int k = j % NS;
+        C2<T> a[R];
+        if constexpr ((nb * PC) % 16 == 0) {
+            const C2<T>* src = in + lpad(j * PC + p);
+    #pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = src[r * (nb * PC / 16 * 17)];
+        } else {
+    #pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = in[lpad((j + r * nb) * PC + p)];
+        }
+        if constexpr (NS > 1) {
+            constexpr int step = L / (NS * R);
+            const int ks = k * step;
+    #pragma unroll
+            for (int r = 1; r < R; ++r) {
+                C2<T> w = tw[r * ks];
+                if (dir > 0) w.y = -w.y;
+                a[r] = cmul(a[r], w);
+            }
+        }
+        dft_small<T, R>(a, dir);
+        const int base = (j / NS) * NS * R + k;
+        if constexpr (DERIV) {
+    #pragma unroll
+            for (int r = 0; r < R; ++r) a[r] = cmuli(a[r], T(wavenumber_odd(base + r * NS, L)) * inv_l);
+        }
+        if constexpr ((NS * PC) % 16 == 0) {
+            C2<T>* dst = out + lpad(base * PC + p);
+    #pragma unroll
+            for (int r = 0; r < R; ++r) dst[r * (NS * PC / 16 * 17)] = a[r];
+        } else {
+    #pragma unroll
+            for (int r = 0; r < R; ++r) out[lpad((base + r * NS) * PC + p)] = a[r];
+        }
+        return;
+    }
     const int PC = 1 << pcshift;
     const int p = t & (PC - 1);
     const int j = t >> pcshift;
@@ -175,7 +221,9 @@ __device__ inline void stockham_butterfly_ct(const C2<T>* in, C2<T>* out, int t,
 // sequence, the stage lengths and the twiddle strides are constants.
 // DERIV: the last stage applies the derivative factor (see
 // stockham_butterfly_ct; forward transforms, dir = -1).
-template <typename T, int L, int NT, int S = 0, int NS = 1, bool DERIV = false>
+// PCS >= 0: the log2 pencil count of the tile as a constant (see
+// stockham_butterfly_ct).
+template <typename T, int L, int NT, int S = 0, int NS = 1, bool DERIV = false, int PCS = -1>
 __device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int pcshift, int dir,
                                       T inv_l = T(0)) {
     constexpr RadixPlanCT P = radix_plan_ct(L);
@@ -183,11 +231,22 @@ __device__ inline C2<T>* block_fft_ct(C2<T>* a, C2<T>* b, const C2<T>* tw, int p
         return a;
     } else {
         constexpr int R = P.r[S];
-        const int nbt = (L / R) << pcshift;
-        for (int t = threadIdx.x; t < nbt; t += NT)
-            stockham_butterfly_ct<T, R, L, NS, DERIV && S + 1 == P.n>(a, b, t, pcshift, tw, dir, inv_l);
+        if constexpr (PCS >= 0) {
+            constexpr int nbt = (L / R) << PCS;
+    #pragma unroll
+            for (int t0 = 0; t0 < nbt; t0 += NT) {
+                const int t = t0 + (int)threadIdx.x;
+                if (nbt % NT == 0 || t < nbt)
+                    stockham_butterfly_ct<T, R, L, NS, DERIV && S + 1 == P.n, PCS>(a, b, t, pcshift, tw, dir,
+                                                                                inv_l);
+            }
+        } else {
+            const int nbt = (L / R) << pcshift;
+            for (int t = threadIdx.x; t < nbt; t += NT)
+                stockham_butterfly_ct<T, R, L, NS, DERIV && S + 1 == P.n>(a, b, t, pcshift, tw, dir, inv_l);
+        }
         __syncthreads();
-        return block_fft_ct<T, L, NT, S + 1, NS * R, DERIV>(b, a, tw, pcshift, dir, inv_l);
+        return block_fft_ct<T, L, NT, S + 1, NS * R, DERIV, PCS>(b, a, tw, pcshift, dir, inv_l);
     }
 }
 

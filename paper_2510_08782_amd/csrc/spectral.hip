@@ -63,6 +63,20 @@ int pc_shift_real(int L, int bytes_per_complex, long long npencils, int threads 
         ++s;
     return s;
 }
+// pc_shift_real when the pencils are not the limit (every large grid), as a
+// constant for the kernels compiled for it.
+constexpr int pc_shift_real_full(int L, int bytes_per_complex, int threads) {
+    int s = 0;
+    while (true) {
+        const long long n = (long long)(1 << (s + 1)) * L;
+        const long long lds = (2 * (n + (n >> 4) + 1) + L) * (long long)bytes_per_complex;
+        if (!((2 << (s + 1)) * L <= threads * kItems && lds <= (long long)kLdsBudget &&
+              s < (threads > kFftThreads ? 6 : 5)))
+            break;
+        ++s;
+    }
+    return s;
+}
 // Same for in-place complex transforms: tiles of PC complex pencils.
 int pc_shift_cplx(int L, int bytes_per_complex, long long npencils, int threads = kFftThreads) {
     const size_t budget = threads > kFftThreads ? kWideLds : kLdsBudget;
@@ -101,13 +115,14 @@ __device__ inline C2<T>* twiddles_to_lds(const FftPlan<T>& pl, C2<T>* tws) {
     return tws;
 }
 
-// Transform of the tile: compiled for length LC when LC > 0, else driven by
-// the runtime plan.
-template <typename T, int LC, int NT = kFftThreads>
+// Transform of the tile: compiled for length LC when LC > 0 (with the
+// constant log2 pencil count PCS when PCS >= 0), else driven by the runtime
+// plan.
+template <typename T, int LC, int NT = kFftThreads, int PCS = -1>
 __device__ inline C2<T>* tile_fft(C2<T>* a, C2<T>* b, const FftPlan<T>& pl, const C2<T>* tw,
                                   int pcshift, int dir) {
     if constexpr (LC > 0)
-        return block_fft_ct<T, LC, NT>(a, b, tw, pcshift, dir);
+        return block_fft_ct<T, LC, NT, 0, 1, false, PCS>(a, b, tw, pcshift, dir);
     else
         return block_fft<T>(a, b, pl, tw, pcshift, dir);
 }
@@ -184,16 +199,20 @@ constexpr int kGroupTime = 9;
 
 // out = [out +] sum_t w_t G_t d/dx_axis F_t over one tile of 2 PC real pencils.
 // The loads of G_t and F_{t+1} are issued before the transforms of step t so
-// that they complete while the LDS passes run.
-template <typename T, int LC, int MT>
+// that they complete while the LDS passes run.  PCS >= 0 (compiled lengths
+// only): the tile's log2 pencil count a.pcshift is known to equal PCS, and
+// the transforms' LDS addressing is compiled for it.
+template <typename T, int LC, int MT, int PCS = -1>
 struct DerivAxisBody {
+    static_assert(PCS < 0 || LC > 0, "a constant pencil count needs a compiled length");
     static constexpr int kBlock = kDerivThreads;
     using Args = DerivArgs<T, MT>;
     __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
         const DerivArgs<T, MT>& a = args_;
         const int L = LC > 0 ? LC : a.pl.L;
-        const int PC = 1 << a.pcshift;
-        const int npshift = a.pcshift + 1;
+        const int pcs = PCS >= 0 ? PCS : a.pcshift;
+        const int PC = 1 << pcs;
+        const int npshift = pcs + 1;
         C2<T>* bufA = reinterpret_cast<C2<T>*>(gan_smem);
         C2<T>* bufB = bufA + lpad_size(PC * L);
         const FftPlan<T>& pl = a.pl;
@@ -218,7 +237,7 @@ struct DerivAxisBody {
             if (q < nitems) {
                 int r, i;
                 item_pos(a.axis, q, L, npshift, r, i);
-                slot[e] = 2 * lpad((i << a.pcshift) + (r & (PC - 1))) + (r >> a.pcshift);
+                slot[e] = 2 * lpad((i << pcs) + (r & (PC - 1))) + (r >> pcs);
                 ok[e] = p0 + r < npen;
                 if (ok[e]) off[e] = pencil_base(dm, a.axis, dm.n[2], p0 + r) + i * stride;
             }
@@ -243,7 +262,7 @@ struct DerivAxisBody {
             C2<T>* X;
             if constexpr (LC > 0) {
                 // the derivative factor is applied by the last forward stage
-                X = block_fft_ct<T, LC, kDerivThreads, 0, 1, true>(bufA, bufB, tw, a.pcshift, -1, inv_l);
+                X = block_fft_ct<T, LC, kDerivThreads, 0, 1, true, PCS>(bufA, bufB, tw, pcs, -1, inv_l);
             } else {
                 X = tile_fft<T, LC, kDerivThreads>(bufA, bufB, pl, tw, a.pcshift, -1);
                 for (int q = threadIdx.x; q < PC * L; q += kDerivThreads) {
@@ -252,7 +271,7 @@ struct DerivAxisBody {
                 }
                 __syncthreads();
             }
-            const C2<T>* Y = tile_fft<T, LC, kDerivThreads>(X, X == bufA ? bufB : bufA, pl, tw, a.pcshift, +1);
+            const C2<T>* Y = tile_fft<T, LC, kDerivThreads, PCS>(X, X == bufA ? bufB : bufA, pl, tw, pcs, +1);
             const T* yflat = reinterpret_cast<const T*>(Y);
             const T wt = T(a.w[t]);
     #pragma unroll
@@ -1213,16 +1232,30 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
         DerivArgs<T, kGroupTime> a;
         fill(a, kGroupTime);
         with_length(L, [&](auto lc) {
-            submit<DerivAxisBody<T, decltype(lc)::value, kGroupTime>,
-                   MergeFamily<decltype(lc)::value, DerivAxisBody<T, decltype(lc)::value, kGroupTime>,
-                               DerivAxisAnyBody<T, kGroupTime>>>(
-                dim3((unsigned)tiles), lds, st, a);
+            constexpr int LCv = decltype(lc)::value;
+            using Fam = MergeFamily<LCv, DerivAxisBody<T, LCv, kGroupTime>, DerivAxisAnyBody<T, kGroupTime>>;
+            constexpr int PF = pc_shift_real_full(LCv > 0 ? LCv : 1, (int)sizeof(C2<T>), kDerivThreads);
+            if constexpr (LCv > 0) {
+                if (a.pcshift == PF) {
+                    submit<DerivAxisBody<T, LCv, kGroupTime, PF>, Fam>(dim3((unsigned)tiles), lds, st, a);
+                    return;
+                }
+            }
+            submit<DerivAxisBody<T, LCv, kGroupTime>, Fam>(dim3((unsigned)tiles), lds, st, a);
         });
     } else {
         DerivArgs<T, kMaxTime> a;
         fill(a, kMaxTime);
         with_length(L, [&](auto lc) {
-            launch_now<DerivAxisBody<T, decltype(lc)::value, kMaxTime>>(dim3((unsigned)tiles), lds, st, a);
+            constexpr int LCv = decltype(lc)::value;
+            constexpr int PF = pc_shift_real_full(LCv > 0 ? LCv : 1, (int)sizeof(C2<T>), kDerivThreads);
+            if constexpr (LCv > 0) {
+                if (a.pcshift == PF) {
+                    launch_now<DerivAxisBody<T, LCv, kMaxTime, PF>>(dim3((unsigned)tiles), lds, st, a);
+                    return;
+                }
+            }
+            launch_now<DerivAxisBody<T, LCv, kMaxTime>>(dim3((unsigned)tiles), lds, st, a);
         });
     }
     return hipGetLastError();

@@ -87,6 +87,18 @@ int pc_shift_cplx(int L, int bytes_per_complex, long long npencils, int threads 
     return s;
 }
 
+constexpr int pc_shift_cplx_full(int L, int bytes_per_complex, int threads = kFftThreads) {
+    const long long budget = threads > kFftThreads ? (long long)kWideLds : (long long)kLdsBudget;
+    int s = 0;
+    while (true) {
+        const long long n = (long long)(1 << (s + 1)) * L;
+        const long long lds = (2 * (n + (n >> 4) + 1) + L) * (long long)bytes_per_complex;
+        if (!((1 << (s + 1)) * L <= threads * kItems && lds <= budget && s < 5)) break;
+        ++s;
+    }
+    return s;
+}
+
 // Pencils along `axis` of an (n0, n1, w) array (w = n2 for real data, n2/2+1
 // for the half spectrum), numbered p = 0..count-1 so that consecutive pencils
 // of the strided axes are adjacent in memory.
@@ -309,14 +321,14 @@ struct R2cRowsArgs {
     InPtrs<TI> ip;
     SpecPtrs<TC> sp;
 };
-template <typename TI, typename TC, int LC>
+template <typename TI, typename TC, int LC, int PCS = -1>
 struct R2cRowsBody {
     static constexpr int kBlock = kFftThreads;
     using Args = R2cRowsArgs<TI, TC>;
     __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
         const Dims& dm = args_.dm;
         const FftPlan<TC>& pl0 = args_.pl0;
-        int pcshift = args_.pcshift;
+        const int pcshift = PCS >= 0 ? PCS : args_.pcshift;
         const InPtrs<TI>& ip = args_.ip;
         const SpecPtrs<TC>& sp = args_.sp;
         using T = TC;
@@ -380,7 +392,7 @@ struct R2cRowsBody {
             }
         }
         __syncthreads();
-        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
+        const C2<T>* Z = tile_fft<T, LC, kFftThreads, PCS>(bufA, bufB, pl, tw, pcshift, -1);
         const int nh = dm.n2h;
         for (int q = threadIdx.x; q < 2 * PC * nh; q += kFftThreads) {
             const int r = q / nh, k = q - r * nh;
@@ -408,7 +420,7 @@ struct C2cAxisArgs {
     int dir;
     SpecPtrs<T> sp;
 };
-template <typename T, int LC, int NT = kFftThreads>
+template <typename T, int LC, int NT = kFftThreads, int PCS = -1>
 struct C2cAxisBody {
     static constexpr int kBlock = NT;
     using Args = C2cAxisArgs<T>;
@@ -416,7 +428,7 @@ struct C2cAxisBody {
         const Dims& dm = args_.dm;
         const FftPlan<T>& pl0 = args_.pl0;
         int axis = args_.axis;
-        int pcshift = args_.pcshift;
+        const int pcshift = PCS >= 0 ? PCS : args_.pcshift;
         int dir = args_.dir;
         const SpecPtrs<T>& sp = args_.sp;
         const int L = LC > 0 ? LC : pl0.L;
@@ -461,7 +473,7 @@ struct C2cAxisBody {
             long long nbase = 0;
             bool nok = false;
             if (next < ntiles) load(next, vals, nbase, nok);
-            const C2<T>* Z = tile_fft<T, LC, NT>(bufA, bufB, pl, tw, pcshift, dir);
+            const C2<T>* Z = tile_fft<T, LC, NT, PCS>(bufA, bufB, pl, tw, pcshift, dir);
     #pragma unroll
             for (int e = 0; e < kItems; ++e) {
                 const int q = threadIdx.x + e * NT;
@@ -494,14 +506,14 @@ struct C2rRowsArgs {
     SpecPtrs<T> sp;
     OutPtrs<T> op;
 };
-template <typename T, int LC>
+template <typename T, int LC, int PCS = -1>
 struct C2rRowsBody {
     static constexpr int kBlock = kFftThreads;
     using Args = C2rRowsArgs<T>;
     __device__ __forceinline__ static void run(const Args& args_, const Blk& bk) {
         const Dims& dm = args_.dm;
         const FftPlan<T>& pl0 = args_.pl0;
-        int pcshift = args_.pcshift;
+        const int pcshift = PCS >= 0 ? PCS : args_.pcshift;
         T scale = args_.scale;
         const SpecPtrs<T>& sp = args_.sp;
         const OutPtrs<T>& op = args_.op;
@@ -547,7 +559,7 @@ struct C2rRowsBody {
             bufA[lpad((i << pcshift) + p)] = cmk(a.x - b.y, a.y + b.x);
         }
         __syncthreads();
-        const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+        const C2<T>* Z = tile_fft<T, LC, kFftThreads, PCS>(bufA, bufB, pl, tw, pcshift, +1);
         constexpr int W = 16 / (int)sizeof(T);
         if (LC > 0 && LC % W == 0 && (reinterpret_cast<unsigned long long>(out) & 15) == 0 &&
             (reinterpret_cast<unsigned long long>(add) & 15) == 0) {
@@ -762,7 +774,7 @@ struct C2cSpecArgs {
     int has_keep;
     SpecPtrs<T> pre;  // kSpecGrad with has_keep: second copy of the direction's spectrum
 };
-template <typename T, int LC, int OP>
+template <typename T, int LC, int OP, int PCS = -1>
 struct C2cSpecBody {
     static constexpr int kBlock = kFftThreads;
     using Args = C2cSpecArgs<T>;
@@ -770,7 +782,7 @@ struct C2cSpecBody {
         const Dims& dm = args_.dm;
         const FftPlan<T>& pl0 = args_.pl0;
         int axis = args_.axis;
-        int pcshift = args_.pcshift;
+        const int pcshift = PCS >= 0 ? PCS : args_.pcshift;
         const SpecOpParams& sop = args_.sop;
         const SpecPtrs<T>& io = args_.io;
         const SpecPtrs<double>& vh = args_.vh;
@@ -806,7 +818,7 @@ struct C2cSpecBody {
                         bufA[lpad(q)] = ok ? src[base + (q >> pcshift) * stride] : cmk(T(0), T(0));
                 }
                 __syncthreads();
-                const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, -1);
+                const C2<T>* Z = tile_fft<T, LC, kFftThreads, PCS>(bufA, bufB, pl, tw, pcshift, -1);
     #pragma unroll
                 for (int e = 0; e < kItems; ++e) {
                     const int q = threadIdx.x + e * kFftThreads;
@@ -872,7 +884,7 @@ struct C2cSpecBody {
                     if (q < nitems) bufA[lpad(q)] = R[c][e];
                 }
                 __syncthreads();
-                const C2<T>* Z = tile_fft<T, LC>(bufA, bufB, pl, tw, pcshift, +1);
+                const C2<T>* Z = tile_fft<T, LC, kFftThreads, PCS>(bufA, bufB, pl, tw, pcshift, +1);
                 C2<T>* dst = io.spec[c];
     #pragma unroll
                 for (int e = 0; e < kItems; ++e) {
@@ -1261,6 +1273,42 @@ hipError_t launch_deriv_axis(const Dims& dm, const SpectralPlans<T>& pl, int axi
     return hipGetLastError();
 }
 
+// A complex axis pass of compiled length LC (0: runtime plan) with NT = nt
+// threads, compiled for the tile's pencil count when it is that of a large
+// grid.
+template <typename T, int LC>
+void submit_c2c_axis(int nt, int sh, dim3 g, size_t lds, hipStream_t st, const C2cAxisArgs<T>& ca) {
+    auto go = [&](auto ntc) {
+        constexpr int NT = decltype(ntc)::value;
+        using Fam = MergeFamily<LC, C2cAxisBody<T, LC, NT>, C2cAxisAnyBody<T, NT>>;
+        constexpr int PF = pc_shift_cplx_full(LC > 0 ? LC : 1, (int)sizeof(C2<T>), NT);
+        if constexpr (LC > 0) {
+            if (sh == PF) {
+                submit<C2cAxisBody<T, LC, NT, PF>, Fam>(g, lds, st, ca);
+                return;
+            }
+        }
+        submit<C2cAxisBody<T, LC, NT>, Fam>(g, lds, st, ca);
+    };
+    if (nt == kWideThreads)
+        go(std::integral_constant<int, kWideThreads>{});
+    else
+        go(std::integral_constant<int, kFftThreads>{});
+}
+// The fused spectral pass, likewise.
+template <typename T, int LC, int OP>
+void submit_c2c_spec(int sh, dim3 g, size_t lds, hipStream_t st, const C2cSpecArgs<T>& ca) {
+    using Fam = MergeFamily<LC, C2cSpecBody<T, LC, OP>, C2cSpecAnyBody<T, OP>>;
+    constexpr int PF = pc_shift_cplx_full(LC > 0 ? LC : 1, (int)sizeof(C2<T>));
+    if constexpr (LC > 0) {
+        if (sh == PF) {
+            submit<C2cSpecBody<T, LC, OP, PF>, Fam>(g, lds, st, ca);
+            return;
+        }
+    }
+    submit<C2cSpecBody<T, LC, OP>, Fam>(g, lds, st, ca);
+}
+
 template <typename TI, typename TC>
 hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* const* in,
                        C2<TC>* const* out, int count, hipStream_t st, int skip_last) {
@@ -1277,11 +1325,19 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         const int sh = pc_shift_real(L, (int)sizeof(C2<TC>), rows);
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
+        const R2cRowsArgs<TI, TC> ra{dm, pl.p[2], sh, ip, sp};
+        const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<TC>));
         with_length(L, [&](auto lc) {
-            submit<R2cRowsBody<TI, TC, decltype(lc)::value>,
-                   MergeFamily<decltype(lc)::value, R2cRowsBody<TI, TC, decltype(lc)::value>,
-                               R2cRowsAnyBody<TI, TC>>>(
-                g, fft_lds_bytes(PC, L, sizeof(C2<TC>)), st, R2cRowsArgs<TI, TC>{dm, pl.p[2], sh, ip, sp});
+            constexpr int LC = decltype(lc)::value;
+            using Fam = MergeFamily<LC, R2cRowsBody<TI, TC, LC>, R2cRowsAnyBody<TI, TC>>;
+            constexpr int PF = pc_shift_real_full(LC > 0 ? LC : 1, (int)sizeof(C2<TC>), kFftThreads);
+            if constexpr (LC > 0) {
+                if (sh == PF) {
+                    submit<R2cRowsBody<TI, TC, LC, PF>, Fam>(g, lds, st, ra);
+                    return;
+                }
+            }
+            submit<R2cRowsBody<TI, TC, LC>, Fam>(g, lds, st, ra);
         });
     }
     for (int axis = 1; axis >= 3 - dm.dim + (skip_last ? 1 : 0); --axis) {
@@ -1293,16 +1349,7 @@ hipError_t launch_rfft(const Dims& dm, const SpectralPlans<TC>& pl, const TI* co
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         const C2cAxisArgs<TC> ca{dm, pl.p[axis], axis, sh, -1, sp};
         const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<TC>));
-        with_length(L, [&](auto lc) {
-            constexpr int LC = decltype(lc)::value;
-            if (nt == kWideThreads)
-                submit<C2cAxisBody<TC, LC, kWideThreads>,
-                       MergeFamily<LC, C2cAxisBody<TC, LC, kWideThreads>, C2cAxisAnyBody<TC, kWideThreads>>>(
-                    g, lds, st, ca);
-            else
-                submit<C2cAxisBody<TC, LC>, MergeFamily<LC, C2cAxisBody<TC, LC>, C2cAxisAnyBody<TC>>>(
-                    g, lds, st, ca);
-        });
+        with_length(L, [&](auto lc) { submit_c2c_axis<TC, decltype(lc)::value>(nt, sh, g, lds, st, ca); });
     }
     return hipGetLastError();
 }
@@ -1328,16 +1375,7 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         dim3 g(strided_blocks((npen + PC - 1) / PC, kTilesPerBlock), count);
         const C2cAxisArgs<T> ca{dm, pl.p[axis], axis, sh, +1, sp};
         const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
-        with_length(L, [&](auto lc) {
-            constexpr int LC = decltype(lc)::value;
-            if (nt == kWideThreads)
-                submit<C2cAxisBody<T, LC, kWideThreads>,
-                       MergeFamily<LC, C2cAxisBody<T, LC, kWideThreads>, C2cAxisAnyBody<T, kWideThreads>>>(
-                    g, lds, st, ca);
-            else
-                submit<C2cAxisBody<T, LC>, MergeFamily<LC, C2cAxisBody<T, LC>, C2cAxisAnyBody<T>>>(
-                    g, lds, st, ca);
-        });
+        with_length(L, [&](auto lc) { submit_c2c_axis<T, decltype(lc)::value>(nt, sh, g, lds, st, ca); });
     }
     {
         const int L = dm.n[2];
@@ -1345,10 +1383,19 @@ hipError_t launch_irfft(const Dims& dm, const SpectralPlans<T>& pl, C2<T>* const
         const int sh = pc_shift_real(L, (int)sizeof(C2<T>), rows);
         const int PC = 1 << sh;
         dim3 g((unsigned)((rows + 2 * PC - 1) / (2 * PC)), count);
+        const C2rRowsArgs<T> ra{dm, pl.p[2], sh, T(scale), sp, op};
+        const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
         with_length(L, [&](auto lc) {
-            submit<C2rRowsBody<T, decltype(lc)::value>,
-                   MergeFamily<decltype(lc)::value, C2rRowsBody<T, decltype(lc)::value>, C2rRowsAnyBody<T>>>(
-                g, fft_lds_bytes(PC, L, sizeof(C2<T>)), st, C2rRowsArgs<T>{dm, pl.p[2], sh, T(scale), sp, op});
+            constexpr int LC = decltype(lc)::value;
+            using Fam = MergeFamily<LC, C2rRowsBody<T, LC>, C2rRowsAnyBody<T>>;
+            constexpr int PF = pc_shift_real_full(LC > 0 ? LC : 1, (int)sizeof(C2<T>), kFftThreads);
+            if constexpr (LC > 0) {
+                if (sh == PF) {
+                    submit<C2rRowsBody<T, LC, PF>, Fam>(g, lds, st, ra);
+                    return;
+                }
+            }
+            submit<C2rRowsBody<T, LC>, Fam>(g, lds, st, ra);
         });
     }
     return hipGetLastError();
@@ -1408,15 +1455,9 @@ hipError_t launch_spec_fused(const Dims& dm, const SpectralPlans<T>& pl, int op,
     const size_t lds = fft_lds_bytes(PC, L, sizeof(C2<T>));
     with_length(L, [&](auto lc) {
         if (op == kSpecGrad)
-            submit<C2cSpecBody<T, decltype(lc)::value, kSpecGrad>,
-                   MergeFamily<decltype(lc)::value, C2cSpecBody<T, decltype(lc)::value, kSpecGrad>,
-                               C2cSpecAnyBody<T, kSpecGrad>>>(
-                dim3(g), lds, st, ca);
+            submit_c2c_spec<T, decltype(lc)::value, kSpecGrad>(sh, dim3(g), lds, st, ca);
         else
-            submit<C2cSpecBody<T, decltype(lc)::value, kSpecPrecond>,
-                   MergeFamily<decltype(lc)::value, C2cSpecBody<T, decltype(lc)::value, kSpecPrecond>,
-                               C2cSpecAnyBody<T, kSpecPrecond>>>(
-                dim3(g), lds, st, ca);
+            submit_c2c_spec<T, decltype(lc)::value, kSpecPrecond>(sh, dim3(g), lds, st, ca);
     });
     return hipGetLastError();
 }

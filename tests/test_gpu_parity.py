@@ -40,8 +40,19 @@ def make_gpu(P, wl, dtype):
                        incompressible=P.incompressible)
 
 
+def inf_tol(P, tol):
+    """Bound on the relative max-norm error.  The FP32 rounding of a spectral
+    derivative grows with the largest wavenumber, n/2 on an n-long axis, against
+    the derivative of the smooth content, so the FP32 bound scales with the
+    longest axis beyond 256; the FP64 bound is the l2 one."""
+    if tol < 1e-8:
+        return tol
+    return tol * max(1.0, max(np.shape(P.m0)) / 256.0)
+
+
 def check_probe(P, G, v, dtype, tol, name):
     say(f"  probe {name}")
+    tinf = inf_tol(P, tol)
     vd = dev(v, dtype)
     Jg, mis = G.eval_objective(vd, with_mismatch=True)
     Jo, miso, _ = P.objective(v, return_parts=True)
@@ -52,7 +63,7 @@ def check_probe(P, G, v, dtype, tol, name):
     assert abs(Jg2 - Jo2) <= tol * abs(Jo2)
     mT = host(G.get_field("state", P.nt))
     assert rel(mT, st["m"][-1]) <= tol, name
-    assert relinf(mT, st["m"][-1]) <= tol, name
+    assert relinf(mT, st["m"][-1]) <= tinf, name
     lam_scale = max(np.abs(st["lam"][-1]).max(), 1e-300)
     lam0 = host(G.get_field("adjoint", 0))
     if np.abs(st["lam"][0]).max() > 0:
@@ -68,11 +79,11 @@ def check_probe(P, G, v, dtype, tol, name):
     errinf = relinf(host(g), go)
     say(f"    J {Jg:.12e} / {Jo:.12e}  grad rel err {err:.3e} (inf {errinf:.3e})")
     assert err <= tol, (name, err)
-    assert errinf <= tol, (name, errinf)
+    assert errinf <= tinf, (name, errinf)
     s, gs = G.apply_precond(g)
     so, gso = ong.precond(P, go)
     assert rel(host(s), so) <= tol, name
-    assert relinf(host(s), so) <= tol, name
+    assert relinf(host(s), so) <= tinf, name
     assert abs(gs - gso) <= 10 * tol * abs(gso), (gs, gso)
 
 
@@ -90,6 +101,10 @@ CASES = [
     # 2-D axis
     ("c2", (192, 16, 24), 2),
     ("c0", (216, 48), 3),
+    # the transforms compiled for length 512 (rows, complex passes, the fused
+    # spectral pass and the body-force derivative), on a grid with enough
+    # pencils that their tiles hold the full pencil count
+    ("c0", (512, 512), 2),
 ]
 
 

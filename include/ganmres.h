@@ -25,8 +25,8 @@
  *     hipStream_t; NULL means the default stream).  One handle per stream;
  *     a handle is not thread-safe.
  *   - The library owns only its workspace, allocated in ganmres_create (and,
- *     for the solver history, at the first ganmres_step) and released by
- *     ganmres_destroy.
+ *     for the solver history and the next direction's spectrum, during the
+ *     first ganmres_step) and released by ganmres_destroy.
  *
  * Discretisation (Sec. 2.2): periodic box [0,2pi)^dim, n_i cells of size
  * h_i = 2 pi / n_i, Fourier pseudo-spectral derivatives, semi-Lagrangian time
